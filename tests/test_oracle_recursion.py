@@ -1,0 +1,207 @@
+"""Pins for oracle.recursion: rescale, MLSP2 layers, entropy expansion, SP2 (CPU only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fermi as F
+from oracle import recursion as R
+from oracle import training as T
+from paper_2605_08523_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def g(key):
+    return GOLD[key]["value"]
+
+
+# --- rescale ----------------------------------------------------------------
+
+@pytest.mark.parametrize("mu", [-0.6, 0.0, 0.4, 1.1])
+def test_rescale_maps_fermi_onto_model_target(mu):
+    """Eq. rescaling: (mu' I - H') beta' = beta (H - mu I), so g(y_i) = f(lambda_i) (1 - f if flipped)."""
+    H = W.random_dense(64, 3)
+    beta0, mu0, kT = 1500.0, 1 / 3, 0.2
+    X0, info = R.rescale(H, mu, kT, beta0, mu0)
+    assert not info["clamped"]
+    lam = np.linalg.eigvalsh(H)
+    y = np.linalg.eigvalsh(X0)
+    f = np.sort(F.fermi(lam, mu, kT))
+    gy = np.sort(T.fermi_target(y, beta0, mu0))
+    if info["flipped"]:
+        gy = np.sort(1 - gy)
+    np.testing.assert_allclose(gy, f, atol=1e-12)
+    np.testing.assert_allclose(X0, info["scale"] * H + info["shift"] * np.eye(64), atol=1e-14)
+    assert info["mu_p"] <= 0.5
+    assert y.min() >= -1e-12 and y.max() <= 1 + 1e-12      # spectrum of H0 inside [0, 1] (Eq. conditions)
+
+
+def test_flip_identity():
+    """Eq. flip: f(x; beta, mu) = 1 - f(1 - x; beta, 1 - mu)."""
+    x = np.linspace(0, 1, 1001)
+    np.testing.assert_allclose(F.fermi(x, 0.3, 0.01), 1 - F.fermi(1 - x, 0.7, 0.01), atol=1e-15)
+
+
+def test_rescale_clamp_and_region():
+    H = W.random_dense(32, 1)
+    lo, hi = F.gershgorin(H)
+    kT = (hi - lo) / 5000.0                      # beta' = 5000 > 1000
+    X0, info = R.rescale(H, 0.0, kT, 1500.0, 1 / 3)
+    assert info["clamped"] and info["beta_p"] == pytest.approx(info["beta_max"])
+    assert info["beta_max"] == pytest.approx(R.beta_max(info["mu_p"], 1500, 1 / 3))
+    y = np.linalg.eigvalsh(X0)
+    assert y.min() >= -1e-9 and y.max() <= 1 + 1e-9
+    # the region's corner: mu' = 1/3 gives beta_max = beta0 (both conditions meet)
+    assert R.beta_max(1 / 3, 1500, 1 / 3) == pytest.approx(1500)
+    assert R.beta_max(0.5, 1500, 1 / 3) == pytest.approx(g("region_beta_max_L26"))
+
+
+def test_rescale_domain_errors():
+    H = W.random_dense(16, 2)
+    lo, hi = F.gershgorin(H)
+    with pytest.raises(R.DomainError):
+        R.rescale(H, hi + 1.0, 0.1, 1500, 1 / 3)
+    with pytest.raises(R.DomainError):
+        R.rescale(H, 0.0, 0.0, 1500, 1 / 3)
+
+
+def test_degenerate_bounds_give_scalar_fermi(paper_model):
+    m = paper_model
+    for c, mu in [(0.2, 0.25), (-0.3, -0.35), (0.0, 0.0)]:
+        H = c * np.eye(8)
+        D, info = R.mlsp2_density(H, mu, 0.05, m.theta, m.beta0, m.mu0)
+        assert info["degenerate"]
+        np.testing.assert_allclose(D, F.fermi(np.array([c]), mu, 0.05)[0] * np.eye(8), atol=1e-7)
+
+
+# --- the paper's 26-layer model -------------------------------------------------
+
+def test_paper_model_error_below_fp32_roundoff(paper_model):
+    m = paper_model
+    err = T.max_model_error(m.theta, m.beta0, m.mu0)
+    assert err < g("model_error_bound_L26")
+    assert R.mlsp2_layers(np.array([m.mu0]), m.theta)[0] == pytest.approx(0.5, abs=1e-9)
+
+
+def test_paper_model_data_properties(paper_model):
+    m = paper_model
+    small = np.sum(np.abs(m.theta[:, 3]) < 1e-8)
+    assert abs(small / m.L - g("half_of_layers_small_d")) < 0.1        # 11 of 26
+    assert m.max_abs_layer() < 1 + g("layer_value_spread")
+
+
+@pytest.mark.parametrize("beta_p", [10.0, 100.0, 500.0, 1000.0])
+@pytest.mark.parametrize("mu_p", [0.05, 0.2, 1 / 3, 0.5])
+def test_region_of_validity(paper_model, beta_p, mu_p):
+    """Fig. 4 (bottom): inside beta' <= beta_max(mu') the model error stays below 10^-7.5."""
+    m = paper_model
+    if beta_p > R.beta_max(mu_p, m.beta0, m.mu0):
+        pytest.skip("outside the region")
+    x = np.linspace(0, 1, 200001)                      # normalized energies H'
+    y = (beta_p / m.beta0) * (x - mu_p) + m.mu0          # Eq. H0
+    P = R.mlsp2_layers(y, m.theta)
+    ref = 1 / (1 + np.exp(beta_p * (mu_p - x)))          # g on the flipped coordinate
+    assert np.max(np.abs(P - ref)) < g("region_error_bound_L26")
+
+
+def test_appendix_selftest(paper_model):
+    """App. A self-test family: 10 seeds, N=100, H = U + U^T, beta, mu drawn inside the region."""
+    m = paper_model
+    for seed in range(10):
+        rng = np.random.default_rng(seed)
+        H = rng.uniform(0, 1, (100, 100))
+        H = H + H.T
+        lo, hi = F.gershgorin(H)
+        beta = rng.uniform(1, (2 / 3 * m.beta0) / (hi - lo))
+        mu = rng.uniform(lo, hi)
+        D, info = R.mlsp2_density(H, mu, 1 / beta, m.theta, m.beta0, m.mu0)
+        ref = F.density(H, mu, 1 / beta)["D"]
+        # the 2-norm error is the largest eigenvalue error, bounded by the model error
+        assert np.linalg.norm(D - ref, 2) < g("model_error_bound_L26")
+
+
+def test_matrix_recursion_equals_scalar_on_eigenvalues(paper_model):
+    m = paper_model
+    H = W.random_dense(48, 9)
+    X0, info = R.rescale(H, 0.1, 0.1, m.beta0, m.mu0)
+    y, V = np.linalg.eigh(X0)
+    P = R.mlsp2_layers(X0, m.theta)
+    np.testing.assert_allclose(P, (V * R.mlsp2_layers(y, m.theta)) @ V.T, atol=1e-11)
+
+
+def test_config_small_dense_against_definition(paper_model):
+    m = paper_model
+    c = W.config_small_dense(0)
+    lam = np.linalg.eigvalsh(c["H"])
+    mu = F.mu_for_filling(lam, c["n_target"], c["kT"])
+    D, info = R.mlsp2_density(c["H"], mu, c["kT"], m.theta, m.beta0, m.mu0)
+    ref = F.density(c["H"], mu, c["kT"])
+    assert np.linalg.norm(D - ref["D"]) / 128 < 1e-9
+    assert abs(np.trace(D) - 64) < 128 * g("model_error_bound_L26")    # N x the model error
+
+
+# --- entropy expansion -----------------------------------------------------------
+
+def test_entropy_expansion_theta_fermi_error_level(paper_model):
+    """theta_fermi + alpha ansatz: the model max error is the ansatz error (Table I row 4, 1.24e-3)."""
+    m = paper_model
+    y = np.linspace(0, 1, 400001)
+    st = R.entropy_scalar(y, m.theta, m.mu0, g("alpha_minimax"))
+    err = np.max(np.abs(st - T.entropy_target(y, m.beta0, m.mu0)))
+    assert abs(err - g("table1_theta_fermi_max_err")) < 2e-5
+
+
+def test_entropy_expansion_matrix_equals_trace_of_scalar(paper_model):
+    m = paper_model
+    H = W.random_dense(40, 4)
+    alpha = g("alpha_minimax")
+    S, info = R.entropy_expansion(H, 0.05, 0.1, m.theta, m.beta0, m.mu0, alpha)
+    X0, _ = R.rescale(H, 0.05, 0.1, m.beta0, m.mu0)
+    y = np.linalg.eigvalsh(X0)
+    assert S == pytest.approx(R.entropy_scalar(y, m.theta, m.mu0, alpha).sum(), rel=1e-10)
+    # and it is close to the exact entropy (ansatz error 1.24e-3 per state at most)
+    Sex = F.entropy(H, 0.05, 0.1)
+    assert abs(S - Sex) < 1.25e-3 * 40
+
+
+# --- SP2, golden ratio, layer count ----------------------------------------------
+
+def test_sp2_embedding_reaches_the_zero_temperature_projector():
+    """Eq. sp2-mu embedded in MLSP2 (App. C) converges to the projector on {lambda < mu} (App. D)."""
+    H, lam = W.gapped_spectrum(80, 30, 0.3, 21)
+    lo, hi = F.gershgorin(H)
+    Hp = (hi * np.eye(80) - H) / (hi - lo)
+    mu_p = (hi - 0.0) / (hi - lo)
+    th = R.sp2_mu_coeffs(mu_p, 60)
+    assert set(map(tuple, th)) <= {(1.0, 0.0, 0.0, 0.0), (-1.0, 2.0, 0.0, 0.0)}
+    D = R.mlsp2_layers(Hp, th)
+    P = F.density(H, 0.0, 1e-6)["D"]
+    np.testing.assert_allclose(D, P, atol=1e-10)
+    np.testing.assert_allclose(D @ D, D, atol=1e-10)
+
+
+def test_golden_ratio_fixed_point_and_slope():
+    """Sec. V.B: (f1 o f0)(phi) = phi and the n-fold alternating map has slope (2 phi)^n at phi."""
+    phi = R.PHI
+    th = np.array([(1.0, 0.0, 0.0, 0.0), (-1.0, 2.0, 0.0, 0.0)] * 6)
+    assert R.mlsp2_layers(np.array([phi]), th[:2])[0] == pytest.approx(phi, abs=1e-15)
+    h = 1e-7
+    for n in (2, 6, 12):
+        v = R.mlsp2_layers(np.array([phi - h, phi + h]), th[:n])
+        assert (v[1] - v[0]) / (2 * h) == pytest.approx((2 * phi) ** n, rel=1e-5)
+
+
+def test_layer_count_closed_forms():
+    assert math.ceil(R.layer_count(1500)) == g("layers_for_beta1500")
+    assert math.ceil(R.layer_count(40)) == g("layers_for_beta40")
+    # n_l = ln(beta'/4)/ln(2 phi) = s ln beta' + o with s = 1/ln(2 phi), o = -ln 4/ln(2 phi)
+    s = (R.layer_count(1e4) - R.layer_count(1e2)) / math.log(1e2)
+    assert round(s, 1) == g("layer_count_slope")
+    assert round(R.layer_count(1.0), 1) == g("layer_count_offset")
+    b10 = R.beta0_for_layers(10)
+    assert round(b10, 1) == g("beta0_for_10_layers")
+    assert round(2 / 3 * b10, 1) == g("beta_p_for_10_layers")
+    assert round(R.temperature_limit_K(1.0), 1) == g("temp_limit_K_per_eV")
