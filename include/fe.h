@@ -1,0 +1,142 @@
+/*
+ * fe.h -- C ABI of the MI355X (gfx950) finite-temperature Fermi-operator expansion library.
+ *
+ * The library evaluates the learned recursive expansion of the Fermi-Dirac density matrix
+ * D = [exp(beta (H - mu I)) + I]^-1 (Sec. II.A) and of the electronic entropy
+ * S = -Tr[D ln D + (I - D) ln(I - D)] (Sec. III.B, Eq. entropy-matrix, per spin, k_B = 1)
+ * for a dense symmetric Hamiltonian H, following Alg. 2 of the paper:
+ *   1. Gershgorin spectral bounds of H,
+ *   2. affine rescale to the model coordinate with the spectrum flip and the region-of-validity
+ *      clamp (Sec. IV.1, Eqs. H', mu', beta', H0, conditions, flip),
+ *   3. L layers  A <- A + d_i X,  X <- a_i X^2 + b_i X + c_i I   (Eq. mlsp2, Alg. 1),
+ *   4. D = A + X (I - (A + X) if the spectrum was flipped), Tr D and sum_ij D_ij^2
+ *      (Sec. IV.3, Eq. tr(D^2)),
+ *   5. the entropy expansion with its own coefficients on Y0 = alpha X0 + (1 - alpha) mu0 I
+ *      and S = 4 ln2 (Tr U - sum_ij U_ij^2), U = A_S + Y (Eq. entropy expansion and its
+ *      output layer).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense, row-major, float64 unless stated, with a leading dimension (ld) in
+ *     elements >= n. H must be exactly symmetric; only its values are read.
+ *   - "device" pointers are HIP device memory owned by the caller. The library never frees
+ *     them. "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call is
+ *     asynchronous on that stream unless its comment says it synchronizes.
+ *   - No call allocates device memory except fe_workspace_create. A workspace must not be
+ *     used by two calls that overlap in time (e.g. on two streams).
+ *   - Return value: FE_OK (0), a positive warning (the result is still produced), or a
+ *     negative error (nothing was enqueued, unless stated). fe_last_error() gives a message.
+ *   - Conditions found on the device (non-finite H, mu outside the spectral bounds) cannot be
+ *     returned by an asynchronous call: the device turns the result into NaN so that it cannot
+ *     be mistaken for a value, and the status is reported in fe_rescale_info.status when the
+ *     caller asks for the info (which synchronizes).
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------- */
+#define FE_OK                  0
+#define FE_WARN_BETA_CLAMPED   1   /* beta' above the model's region of validity was clamped to
+                                      beta_max (Eq. conditions); D is then the density matrix at
+                                      the clamped temperature, as the paper's reference code does */
+#define FE_ERR_ARG            -1   /* bad argument (null pointer, n < 1, ld < n, L < 1, ...) */
+#define FE_ERR_DOMAIN         -2   /* kT <= 0, or mu outside (eps_min, eps_max) */
+#define FE_ERR_HIP            -3   /* a HIP runtime call failed */
+#define FE_ERR_NONFINITE      -4   /* H holds a NaN or an infinity */
+#define FE_ERR_NO_CONVERGENCE -5   /* the coefficient fit did not reach its tolerance */
+#define FE_ERR_WORKSPACE      -6   /* the workspace is too small for the request */
+#define FE_ERR_RANGE          -7   /* the model's layer values leave the 16-bit operand range */
+
+/* ---- precision of the layer products ---------------------------------------------- */
+#define FE_PREC_FP64    0   /* FP64 MFMA products, FP64 storage */
+#define FE_PREC_FP32    1   /* FP32 MFMA products, FP32 storage */
+#define FE_PREC_FP16X2  2   /* X = hi + 2^-11 lo with FP16 hi/lo; X^2 from three FP16 MFMA products
+                               (hi*hi, hi*lo, lo*hi) with FP32 accumulation; the lo*lo term is
+                               dropped (Sec. V.A, Eq. emulated matmul). FP32 master copy of X. */
+#define FE_PREC_BF16X2  3   /* same with BF16 hi/lo (no lo scaling) */
+
+/* ---- model: one coefficient table ---------------------------------------------------- */
+typedef struct {
+    int32_t L;            /* number of layers, >= 1 */
+    double beta0;         /* training inverse temperature in the model coordinate (> 0) */
+    double mu0;           /* training chemical potential in the model coordinate, in (0, 1) */
+    const double* theta;  /* host, L x 4 row-major: theta[4i + 0..3] = (a_i, b_i, c_i, d_i) of
+                             Eq. (mlsp2): x <- a x^2 + b x + c, A <- A + d x */
+} fe_model;
+
+/* ---- result of the rescale (Sec. IV.1) ------------------------------------------------ */
+typedef struct {
+    double emin, emax;    /* Gershgorin bounds of H */
+    double mu_p;          /* mu' after the flip, in [0, 1/2] */
+    double beta_p;        /* beta' after the clamp */
+    double beta_max;      /* min(mu0/mu', (1 - mu0)/(1 - mu')) beta0 (Eq. conditions) */
+    double scale, shift;  /* X0 = scale * H + shift * I */
+    int32_t flipped;      /* 1 if mu' > 1/2 and the spectrum was flipped (Eq. flip) */
+    int32_t clamped;      /* 1 if beta' was clamped */
+    int32_t degenerate;   /* 1 if eps_max == eps_min (H = c I): X0 = y I with the exact y */
+    int32_t status;       /* FE_OK, FE_WARN_BETA_CLAMPED, FE_ERR_DOMAIN or FE_ERR_NONFINITE */
+} fe_rescale_info;
+
+/* ---- workspace ------------------------------------------------------------------------ */
+typedef struct fe_workspace fe_workspace;
+
+/* Allocate device scratch for matrices up to max_n (single-matrix calls) and for batches of up
+ * to max_batch matrices whose padded sizes sum to at most batch_elems elements (0 and 0 for no
+ * batch capacity). Allocates on the current HIP device. */
+int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, fe_workspace** ws);
+int fe_workspace_destroy(fe_workspace* ws);
+
+/* ---- single matrix ---------------------------------------------------------------------- */
+
+/* Steps 1-2 of Alg. 2 (Gershgorin bounds, Eqs. H', mu', beta', flip, conditions, H0).
+ * H: device, n x n (ld ldh). X0: device float32 n x n (ld ldx) or NULL: receives
+ * X0 = (beta'/beta0)(H' - mu' I) + mu0 I. info: host or NULL; if non-NULL the call
+ * synchronizes the stream and fills it. Returns FE_WARN_BETA_CLAMPED if clamped (only when
+ * info is given), or the info's error status. */
+int fe_rescale(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
+               float* X0, int64_t ldx, fe_rescale_info* info, fe_workspace* ws, void* stream);
+
+/* Density matrix by Alg. 2 (steps 1-4) with model m in precision prec (FE_PREC_*).
+ * D: device, n x n (ld ldd), float32 if d_is_fp64 == 0 else float64; exactly symmetric.
+ *    In the 16-bit and FP32 modes D carries FP32 values (also when stored as float64).
+ * trD, trD2: device float64 scalars or NULL: Tr D and sum_ij D_ij^2 accumulated in FP64.
+ * info: as for fe_rescale (synchronizes when non-NULL). */
+int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64, int64_t ldd,
+                      double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
+                      void* stream);
+
+/* Entropy by Alg. 2 (steps 1-2 and 5) with entropy coefficients mS (trained at the same
+ * (beta0, mu0) as the density model, or the density model itself) and rescale alpha
+ * (Sec. III.B; |alpha| <= 1). S: device float64 scalar (per spin, k_B = 1). */
+int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* mS, double alpha, int32_t prec, double* S,
+                      fe_rescale_info* info, fe_workspace* ws, void* stream);
+
+/* ---- helpers ---------------------------------------------------------------------------- */
+
+/* SP2 for a known chemical potential embedded in the layer form (Eq. sp2-mu; App. C):
+ * theta_out (host, L x 4) receives (1,0,0,0) for X^2 and (-1,2,0,0) for 2X - X^2. */
+int fe_sp2_coeffs(double mu_p, int32_t L, double* theta_out);
+
+/* Layer count estimate n_l = ln(beta'/4) / ln(2 phi), phi the inverse golden ratio
+ * (Sec. V.B, Eq. layer count). */
+double fe_layer_count(double beta_p);
+
+/* Message for the last error on the calling thread (static storage, never NULL). */
+const char* fe_last_error(void);
+
+/* Library version string. */
+const char* fe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

@@ -1,0 +1,254 @@
+"""Python binding of libfe (the C ABI in include/fe.h): argument marshalling only.
+
+Every step of the expansion runs in the HIP library. PyTorch provides device memory and the
+current HIP stream; no computation of the method happens here. If the library has not been
+built (``python -m paper_2605_08523_amd.build``) every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfe.so")
+
+FE_OK = 0
+FE_WARN_BETA_CLAMPED = 1
+FE_ERR_ARG = -1
+FE_ERR_DOMAIN = -2
+FE_ERR_HIP = -3
+FE_ERR_NONFINITE = -4
+FE_ERR_NO_CONVERGENCE = -5
+FE_ERR_WORKSPACE = -6
+FE_ERR_RANGE = -7
+
+PREC = {"fp64": 0, "fp32": 1, "fp16x2": 2, "bf16x2": 3}
+
+
+class FeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfe error {code}: {msg}")
+        self.code = code
+
+
+class fe_model(C.Structure):
+    _fields_ = [("L", C.c_int32), ("beta0", C.c_double), ("mu0", C.c_double),
+                ("theta", C.POINTER(C.c_double))]
+
+
+class fe_rescale_info(C.Structure):
+    _fields_ = [("emin", C.c_double), ("emax", C.c_double), ("mu_p", C.c_double),
+                ("beta_p", C.c_double), ("beta_max", C.c_double), ("scale", C.c_double),
+                ("shift", C.c_double), ("flipped", C.c_int32), ("clamped", C.c_int32),
+                ("degenerate", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_D = C.c_double
+_I32 = C.c_int32
+_I64 = C.c_int64
+
+# name -> (restype, argtypes); every symbol declared in include/fe.h
+SIGNATURES = {
+    "fe_workspace_create": (_I32, [_I64, _I32, _I64, C.POINTER(_P)]),
+    "fe_workspace_destroy": (_I32, [_P]),
+    "fe_rescale": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _P, _I64,
+                          C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_expand_density": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _P, _I32, _I64,
+                                 _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_expand_entropy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _D, _I32, _P,
+                                 C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_sp2_coeffs": (_I32, [_D, _I32, C.POINTER(_D)]),
+    "fe_layer_count": (_D, [_D]),
+    "fe_last_error": (C.c_char_p, []),
+    "fe_version": (C.c_char_p, []),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libfe.so from the package directory (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2605_08523_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise FeError(rc, lib().fe_last_error().decode())
+    return rc
+
+
+@dataclass
+class _ModelRef:
+    """Keeps the ctypes struct and its coefficient buffer alive together."""
+    struct: fe_model
+    theta: np.ndarray
+
+
+def make_model(theta, beta0: float, mu0: float) -> _ModelRef:
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, 4))
+    m = fe_model(th.shape[0], float(beta0), float(mu0), th.ctypes.data_as(C.POINTER(C.c_double)))
+    return _ModelRef(m, th)
+
+
+def _model_of(model) -> _ModelRef:
+    if isinstance(model, _ModelRef):
+        return model
+    return make_model(model.theta, model.beta0, model.mu0)
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_H(H):
+    import torch
+    if not isinstance(H, torch.Tensor) or H.device.type != "cuda" or H.dtype != torch.float64:
+        raise TypeError("H must be a float64 tensor on a HIP device")
+    if H.dim() != 2 or H.shape[0] != H.shape[1]:
+        raise ValueError("H must be square")
+    if H.stride(1) != 1:
+        raise ValueError("H must be row-major (unit column stride)")
+    return H.shape[0], H.stride(0)
+
+
+class Workspace:
+    """Device scratch of the library (fe_workspace_create); sized for matrices up to max_n."""
+
+    def __init__(self, max_n: int, max_batch: int = 0, batch_elems: int = 0):
+        p = C.c_void_p()
+        _check(lib().fe_workspace_create(int(max_n), int(max_batch), int(batch_elems), C.byref(p)))
+        self._p = p
+        self.max_n = int(max_n)
+
+    @property
+    def handle(self):
+        return self._p
+
+    def close(self):
+        if self._p:
+            lib().fe_workspace_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ws_cache: dict = {}
+
+
+def workspace(n: int) -> Workspace:
+    """A cached workspace large enough for n (grown on demand, per device)."""
+    import torch
+    dev = torch.cuda.current_device()
+    ws = _ws_cache.get(dev)
+    if ws is None or ws.max_n < n:
+        if ws is not None:
+            torch.cuda.synchronize()
+            ws.close()
+        ws = Workspace(max(n, 128))
+        _ws_cache[dev] = ws
+    return ws
+
+
+def rescale(H, mu: float, kT: float, model, want_X0: bool = True, ws: Workspace | None = None):
+    """fe_rescale: returns (X0 float32 tensor or None, info dict). Synchronizes."""
+    import torch
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    mr = _model_of(model)
+    X0 = torch.empty((n, n), dtype=torch.float32, device=H.device) if want_X0 else None
+    info = fe_rescale_info()
+    rc = _check(lib().fe_rescale(C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT),
+                                 C.byref(mr.struct), C.c_void_p(X0.data_ptr() if want_X0 else 0),
+                                 n, C.byref(info), ws.handle, _stream_ptr()))
+    d = info.as_dict()
+    d["rc"] = rc
+    return X0, d
+
+
+def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=None,
+                   out_dtype=None, want_info: bool = False, traces: bool = True,
+                   ws: Workspace | None = None):
+    """fe_expand_density. Returns (D, trD, trD2, info): D a tensor (float32 unless out_dtype or
+    ``out`` says float64), trD/trD2 0-d float64 device tensors (or None), info a dict or None.
+    Asynchronous on the current stream unless want_info."""
+    import torch
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    mr = _model_of(model)
+    if out is None:
+        out = torch.empty((n, n), dtype=out_dtype or torch.float32, device=H.device)
+    if out.dtype not in (torch.float32, torch.float64) or out.stride(1) != 1:
+        raise TypeError("out must be a row-major float32/float64 device tensor")
+    tr = torch.empty(2, dtype=torch.float64, device=H.device) if traces else None
+    info = fe_rescale_info() if want_info else None
+    rc = _check(lib().fe_expand_density(
+        C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct), PREC[prec],
+        C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64), out.stride(0),
+        C.c_void_p(tr.data_ptr() if traces else 0),
+        C.c_void_p(tr.data_ptr() + 8 if traces else 0),
+        C.byref(info) if want_info else None, ws.handle, _stream_ptr()))
+    d = None
+    if want_info:
+        d = info.as_dict()
+        d["rc"] = rc
+    return out, (tr[0] if traces else None), (tr[1] if traces else None), d
+
+
+def expand_entropy(H, mu: float, kT: float, model_s, alpha: float, prec: str = "fp16x2",
+                   want_info: bool = False, ws: Workspace | None = None):
+    """fe_expand_entropy. Returns (S 0-d float64 device tensor, info dict or None)."""
+    import torch
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    mr = _model_of(model_s)
+    S = torch.empty((), dtype=torch.float64, device=H.device)
+    info = fe_rescale_info() if want_info else None
+    rc = _check(lib().fe_expand_entropy(
+        C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct), float(alpha),
+        PREC[prec], C.c_void_p(S.data_ptr()), C.byref(info) if want_info else None, ws.handle,
+        _stream_ptr()))
+    d = None
+    if want_info:
+        d = info.as_dict()
+        d["rc"] = rc
+    return S, d
+
+
+def sp2_coeffs(mu_p: float, L: int) -> np.ndarray:
+    out = np.zeros((L, 4))
+    _check(lib().fe_sp2_coeffs(float(mu_p), int(L), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def layer_count(beta_p: float) -> float:
+    return float(lib().fe_layer_count(float(beta_p)))
+
+
+def version() -> str:
+    return lib().fe_version().decode()

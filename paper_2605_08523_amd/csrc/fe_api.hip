@@ -1,0 +1,342 @@
+// Host side of the C ABI declared in include/fe.h: argument checks, the workspace, and the
+// launch sequence of Alg. 2 (bounds -> rescale -> L layers -> traces) on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "fe_internal.h"
+
+namespace fe {
+int split_tile_ok(int tile);
+int small_f64_max_np();
+}  // namespace fe
+
+struct fe_workspace {
+    int device = 0;
+    int64_t max_n = 0;
+    int64_t np_cap = 0;           // largest padded size a single-matrix call may use
+    size_t slot_bytes = 0;
+    void* slot[2] = {nullptr, nullptr};           // 0: density, 1: entropy
+    fe::Params* params = nullptr;                 // [2]
+    fe::BoundsPartial* bparts = nullptr;          // [2][kMaxBoundsBlocks]
+    fe::TracePartial* tparts = nullptr;           // [2][kMaxTiles]
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(FE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FE_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+    } while (0)
+
+constexpr int kMaxLayers = 4096;
+constexpr double kDSkip = 1e-8;   // accumulator weights below this are skipped (Sec. V.A)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int check_model(const fe_model* m, const char* name) {
+    if (!m) return fail(FE_ERR_ARG, std::string(name) + " is NULL");
+    if (m->L < 1 || m->L > kMaxLayers) return fail(FE_ERR_ARG, std::string(name) + ": L out of range");
+    if (!m->theta) return fail(FE_ERR_ARG, std::string(name) + ": theta is NULL");
+    if (!(m->beta0 > 0.0) || !isfinite(m->beta0))
+        return fail(FE_ERR_ARG, std::string(name) + ": beta0 must be positive");
+    if (!(m->mu0 > 0.0 && m->mu0 < 1.0)) return fail(FE_ERR_ARG, std::string(name) + ": mu0 must lie in (0, 1)");
+    for (int i = 0; i < 4 * m->L; ++i)
+        if (!isfinite(m->theta[i])) return fail(FE_ERR_ARG, std::string(name) + ": non-finite coefficient");
+    return FE_OK;
+}
+
+// Largest |x_i| over the layers for model inputs in [0, 1] (after the entropy rescale when
+// alpha != 1): the 16-bit operands must stay well inside the FP16 range (hi is scaled by 2^11
+// inside the product).
+double layer_range(const fe_model* m, double alpha) {
+    double mx = 0.0;
+    const int kPts = 1025;
+    for (int k = 0; k < kPts; ++k) {
+        double y = (double)k / (kPts - 1);
+        double x = alpha * (y - m->mu0) + m->mu0;
+        mx = fmax(mx, fabs(x));
+        for (int i = 0; i < m->L; ++i) {
+            const double* t = m->theta + 4 * i;
+            x = t[0] * x * x + t[1] * x + t[2];
+            mx = fmax(mx, fabs(x));
+        }
+    }
+    return mx;
+}
+
+int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, fe_workspace* ws) {
+    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
+    if (!H) return fail(FE_ERR_ARG, "H is NULL");
+    if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
+    if (ldh < n) return fail(FE_ERR_ARG, "ldh < n");
+    if (!(kT > 0.0) || !isfinite(kT)) return fail(FE_ERR_DOMAIN, "kT must be positive and finite");
+    if (!isfinite(mu)) return fail(FE_ERR_DOMAIN, "mu must be finite");
+    if (n > ws->max_n) return fail(FE_ERR_WORKSPACE, "n exceeds the workspace's max_n");
+    return FE_OK;
+}
+
+int select_tile(int64_t n) {
+    const char* env = getenv("FE_TILE");
+    if (env) {
+        int t = atoi(env);
+        if (fe::split_tile_ok(t)) return t;
+    }
+    return n > 8192 ? 256 : 128;
+}
+
+int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
+    FE_HIP(hipStreamSynchronize(s));
+    fe::Params p;
+    FE_HIP(hipMemcpy(&p, ws->params + which, sizeof(p), hipMemcpyDeviceToHost));
+    info->emin = p.emin;
+    info->emax = p.emax;
+    info->mu_p = p.mu_p;
+    info->beta_p = p.beta_p;
+    info->beta_max = p.beta_max;
+    info->scale = p.scale;
+    info->shift = p.shift;
+    info->flipped = p.flipped;
+    info->clamped = p.clamped;
+    info->degenerate = p.degenerate;
+    info->status = p.status;
+    if (p.status == FE_ERR_DOMAIN) return fail(FE_ERR_DOMAIN, "mu lies outside the Gershgorin bounds of H");
+    if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
+    return p.status;
+}
+
+// Slot carving for the precision modes (np x np elements each).
+struct SplitBufs {
+    float *X, *A;
+    uint16_t *hi[2], *lo[2];
+};
+SplitBufs carve_split(void* base, int64_t np) {
+    SplitBufs b;
+    const size_t e = (size_t)np * np;
+    b.X = static_cast<float*>(base);
+    b.A = b.X + e;
+    uint16_t* h = reinterpret_cast<uint16_t*>(b.A + e);
+    b.hi[0] = h;
+    b.hi[1] = h + e;
+    b.lo[0] = h + 2 * e;
+    b.lo[1] = h + 3 * e;
+    return b;
+}
+struct WideBufs {
+    void *X[2], *A;
+};
+WideBufs carve_wide(void* base, int64_t np, size_t elem) {
+    WideBufs b;
+    const size_t e = (size_t)np * np * elem;
+    char* c = static_cast<char*>(base);
+    b.X[0] = c;
+    b.X[1] = c + e;
+    b.A = c + 2 * e;
+    return b;
+}
+
+// Runs Alg. 2 for one matrix on workspace slot `which`. alpha = 1 and entropy = 0 give the
+// density; entropy = 1 gives S (no matrix output).
+int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
+                  int prec, double alpha, int entropy, void* D, int d_is_fp64, int64_t ldd,
+                  double* trD, double* trD2, double* S, fe_rescale_info* info, fe_workspace* ws,
+                  hipStream_t s, int which) {
+    int rc = check_common(H, n, ldh, mu, kT, ws);
+    if (rc) return rc;
+    rc = check_model(m, entropy ? "entropy model" : "model");
+    if (rc) return rc;
+    if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X2) return fail(FE_ERR_ARG, "unknown precision");
+    if (!entropy && D && ldd < n) return fail(FE_ERR_ARG, "ldd < n");
+    if (entropy && !(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
+    const bool split = prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2;
+    if (split && layer_range(m, alpha) > 16.0)
+        return fail(FE_ERR_RANGE, "layer values exceed the 16-bit operand range");
+
+    int out_mode = 2;
+    if (!entropy && D) out_mode = d_is_fp64 ? 1 : 0;
+    const double* th = m->theta;
+    auto dval = [&](int i) {
+        const double d = th[4 * i + 3];
+        return (prec != FE_PREC_FP64 && fabs(d) < kDSkip) ? 0.0 : d;
+    };
+
+    fe::Params* P = ws->params + which;
+    fe::BoundsPartial* bp = ws->bparts + (size_t)which * fe::kMaxBoundsBlocks;
+    fe::TracePartial* tp = ws->tparts + (size_t)which * fe::kMaxTiles;
+    FE_HIP(fe::launch_bounds_params(H, n, ldh, mu, kT, m->beta0, m->mu0, bp, P, s));
+
+    int npart = 1;
+    if (prec == FE_PREC_FP64 && round_up(n, 16) <= fe::small_f64_max_np()) {
+        const int64_t np = round_up(n, 16);
+        WideBufs b = carve_wide(ws->slot[which], np, sizeof(double));
+        fe::RescaleArgs ra{};
+        ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = P;
+        ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = 0.0;
+        ra.X64 = static_cast<double*>(b.X[0]); ra.A64 = static_cast<double*>(b.A);
+        ra.mode = 2;
+        FE_HIP(fe::launch_rescale(ra, s));
+        if (m->L > fe::kSmallMaxL) return fail(FE_ERR_ARG, "too many layers for the small FP64 path");
+        fe::SmallArgs sa{};
+        sa.n = n; sa.np = np; sa.X0 = static_cast<double*>(b.X[0]); sa.L = m->L;
+        memcpy(sa.theta, th, sizeof(double) * 4 * m->L);
+        sa.d0 = dval(0); sa.out_mode = out_mode; sa.entropy = entropy; sa.D = D; sa.ldd = ldd;
+        sa.P = P; sa.partials = tp;
+        FE_HIP(fe::launch_small_f64(sa, s));
+    } else if (split) {
+        const int tile = select_tile(n);
+        const int64_t np = round_up(n, tile);
+        if (np > ws->np_cap) return fail(FE_ERR_WORKSPACE, "padded size exceeds the workspace");
+        SplitBufs b = carve_split(ws->slot[which], np);
+        const int bf = prec == FE_PREC_BF16X2;
+        fe::RescaleArgs ra{};
+        ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = P;
+        ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
+        ra.X32 = b.X; ra.A32 = b.A; ra.hi = b.hi[0]; ra.lo = b.lo[0];
+        ra.mode = 0; ra.bf16 = bf;
+        FE_HIP(fe::launch_rescale(ra, s));
+        const int T = (int)(np / tile);
+        npart = T * (T + 1) / 2;
+        if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
+        for (int i = 0; i < m->L; ++i) {
+            fe::LayerArgs la{};
+            la.np = np; la.n = n;
+            la.hi_in = b.hi[i & 1]; la.lo_in = b.lo[i & 1];
+            la.hi_out = b.hi[(i + 1) & 1]; la.lo_out = b.lo[(i + 1) & 1];
+            la.X = b.X; la.A = b.A;
+            la.a = (float)th[4 * i]; la.b = (float)th[4 * i + 1]; la.c = (float)th[4 * i + 2];
+            la.d_next = (i + 1 < m->L) ? (float)dval(i + 1) : 0.0f;
+            la.last = (i + 1 == m->L);
+            la.out_mode = out_mode; la.entropy = entropy; la.D = D; la.ldd = ldd;
+            la.P = P; la.partials = tp;
+            FE_HIP(fe::launch_layer_split(la, bf, tile, s));
+        }
+    } else {
+        return fail(FE_ERR_ARG, "precision mode not available for this size in this build");
+    }
+    FE_HIP(fe::launch_reduce_partials(tp, npart, trD, trD2, S, P, s));
+    if (info) return read_info(ws, which, s, info);
+    return FE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fe_last_error(void) { return g_err.c_str(); }
+
+const char* fe_version(void) { return "fe-mi355x 0.1 (gfx950)"; }
+
+int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, fe_workspace** out) {
+    if (!out) return fail(FE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_n < 1) return fail(FE_ERR_ARG, "max_n must be >= 1");
+    if (max_batch < 0 || batch_elems < 0) return fail(FE_ERR_ARG, "negative batch capacity");
+    fe_workspace* ws = new fe_workspace();
+    FE_HIP(hipGetDevice(&ws->device));
+    ws->max_n = max_n;
+    ws->np_cap = round_up(max_n, 256);
+    ws->slot_bytes = (size_t)ws->np_cap * ws->np_cap * 24;   // FP64 mode: 3 doubles per element
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMalloc(&ws->slot[k], ws->slot_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->params), 2 * sizeof(fe::Params));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void**>(&ws->bparts), 2 * fe::kMaxBoundsBlocks * sizeof(fe::BoundsPartial));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void**>(&ws->tparts), 2 * (size_t)fe::kMaxTiles * sizeof(fe::TracePartial));
+    if (e != hipSuccess) {
+        fe_workspace_destroy(ws);
+        return hip_fail(e, "hipMalloc (workspace)");
+    }
+    *out = ws;
+    return FE_OK;
+}
+
+int fe_workspace_destroy(fe_workspace* ws) {
+    if (!ws) return FE_OK;
+    for (int k = 0; k < 2; ++k)
+        if (ws->slot[k]) (void)hipFree(ws->slot[k]);
+    if (ws->params) (void)hipFree(ws->params);
+    if (ws->bparts) (void)hipFree(ws->bparts);
+    if (ws->tparts) (void)hipFree(ws->tparts);
+    delete ws;
+    return FE_OK;
+}
+
+int fe_rescale(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
+               float* X0, int64_t ldx, fe_rescale_info* info, fe_workspace* ws, void* stream) {
+    int rc = check_common(H, n, ldh, mu, kT, ws);
+    if (rc) return rc;
+    rc = check_model(m, "model");
+    if (rc) return rc;
+    if (X0 && ldx < n) return fail(FE_ERR_ARG, "ldx < n");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FE_HIP(fe::launch_bounds_params(H, n, ldh, mu, kT, m->beta0, m->mu0, ws->bparts, ws->params, s));
+    if (X0) {
+        const int64_t np = round_up(n, 16);
+        WideBufs b = carve_wide(ws->slot[0], np, sizeof(float));
+        fe::RescaleArgs ra{};
+        ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = ws->params;
+        ra.alpha = 1.0; ra.mu0 = m->mu0; ra.d0 = 0.0;
+        ra.X32 = static_cast<float*>(b.X[0]); ra.A32 = static_cast<float*>(b.A);
+        ra.mode = 1; ra.X0out = X0; ra.ldx = ldx;
+        FE_HIP(fe::launch_rescale(ra, s));
+    }
+    if (info) return read_info(ws, 0, s, info);
+    return FE_OK;
+}
+
+int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64, int64_t ldd,
+                      double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
+                      void* stream) {
+    return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
+                         info, ws, static_cast<hipStream_t>(stream), 0);
+}
+
+int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* mS, double alpha, int32_t prec, double* S,
+                      fe_rescale_info* info, fe_workspace* ws, void* stream) {
+    if (!S) return fail(FE_ERR_ARG, "S is NULL");
+    return run_expansion(H, n, ldh, mu, kT, mS, prec, alpha, 1, nullptr, 0, 0, nullptr, nullptr, S,
+                         info, ws, static_cast<hipStream_t>(stream), 1);
+}
+
+int fe_sp2_coeffs(double mu_p, int32_t L, double* theta_out) {
+    if (!theta_out || L < 1) return fail(FE_ERR_ARG, "bad arguments");
+    if (!(mu_p > 0.0 && mu_p < 1.0)) return fail(FE_ERR_DOMAIN, "mu' must lie in (0, 1)");
+    double m = mu_p;
+    for (int i = 0; i < L; ++i) {
+        const double sq = m * m, up = 2.0 * m - m * m;
+        double* t = theta_out + 4 * i;
+        if (fabs(sq - mu_p) < fabs(up - mu_p)) {   // X^2 keeps the image of mu' closer
+            t[0] = 1.0; t[1] = 0.0; t[2] = 0.0; t[3] = 0.0;
+            m = sq;
+        } else {                                   // 2X - X^2
+            t[0] = -1.0; t[1] = 2.0; t[2] = 0.0; t[3] = 0.0;
+            m = up;
+        }
+    }
+    return FE_OK;
+}
+
+double fe_layer_count(double beta_p) {
+    const double phi = 2.0 / (1.0 + sqrt(5.0));
+    return log(beta_p / 4.0) / log(2.0 * phi);
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP translation units of libfe.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fe.h"
+
+namespace fe {
+
+// Device-resident rescale parameters, produced by the prologue kernels and read by the rescale
+// and final-layer kernels so that no host round trip is needed between them.
+struct Params {
+    double emin, emax;
+    double mu_p, beta_p, beta_max;
+    double scale, shift;   // X0 = scale * H + shift * I
+    int32_t flipped, clamped, degenerate, status;
+};
+
+// Per-block partial results of the Gershgorin pass.
+struct BoundsPartial {
+    double lo, hi;
+    int32_t nonfinite, pad;
+};
+
+// Per-tile partial traces of the last layer, reduced in a fixed order.
+struct TracePartial {
+    double tr, sq;   // sum of diagonal entries, sum of squared entries
+};
+
+// A slot of device scratch for one matrix (layout depends on the precision mode).
+struct Slot {
+    void* base;
+    size_t bytes;
+};
+
+constexpr int kMaxBoundsBlocks = 4096;
+constexpr int kMaxTiles = 1 << 16;
+
+// ---- launchers (one per translation unit; all asynchronous on `s`) ------------------------
+
+// Gershgorin bounds and the rescale parameters of Sec. IV.1 into *P.
+hipError_t launch_bounds_params(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                                double beta0, double mu0, BoundsPartial* partials, Params* P,
+                                hipStream_t s);
+
+// X0 = scale H + shift I into the working copies of a padded np x np matrix. Entries outside
+// n x n are zero. `alpha` rescales towards mu0 for the entropy input:
+// Y0 = alpha X0 + (1 - alpha) mu0 I (alpha = 1 for the density).
+// mode 0: 16-bit split (X32, A32, hi, lo; T16 selected by bf16 flag)
+// mode 1: FP32 (X32, A32)
+// mode 2: FP64 (X64, A64)
+struct RescaleArgs {
+    const double* H;
+    int64_t n, ldh, np;
+    const Params* P;
+    double alpha, mu0, d0;
+    float* X32;
+    float* A32;
+    double* X64;
+    double* A64;
+    uint16_t* hi;
+    uint16_t* lo;
+    int mode;
+    int bf16;
+    float* X0out;       // optional float32 n x n copy of X0 (fe_rescale)
+    int64_t ldx;
+};
+hipError_t launch_rescale(const RescaleArgs& a, hipStream_t s);
+
+// One layer of the split-precision (FP16x2 / BF16x2) recursion with the fused epilogue.
+struct LayerArgs {
+    int64_t np;             // padded size, multiple of the tile size
+    int64_t n;              // real size (for output masking and traces)
+    const uint16_t* hi_in;  // current operands (np x np, full symmetric)
+    const uint16_t* lo_in;
+    uint16_t* hi_out;       // next-layer operands (unused on the last layer)
+    uint16_t* lo_out;
+    float* X;               // FP32 master (upper triangle maintained), in place
+    float* A;               // accumulator (upper triangle maintained), in place
+    float a, b, c;          // this layer's coefficients
+    float d_next;           // next layer's accumulator weight (0 = skip)
+    int last;               // 1 on the last layer
+    int out_mode;           // last layer: 0 = D float32, 1 = D float64, 2 = traces only
+    int entropy;            // last layer: partials hold U traces for S (no D written)
+    void* D;
+    int64_t ldd;
+    const Params* P;        // flip flag for the last layer
+    TracePartial* partials; // one per tile on the last layer
+};
+hipError_t launch_layer_split(const LayerArgs& a, int bf16, int tile, hipStream_t s);
+
+// Whole recursion for np <= 128 in FP64 inside one workgroup's LDS. The coefficients travel
+// by value with the launch.
+constexpr int kSmallMaxL = 96;
+struct SmallArgs {
+    int64_t n, np;
+    const double* X0;       // np x np FP64 start matrix (full)
+    double theta[4 * kSmallMaxL];
+    int L;
+    double d0;
+    int out_mode;           // 0 = D float32, 1 = D float64, 2 = traces only
+    int entropy;
+    void* D;
+    int64_t ldd;
+    const Params* P;
+    TracePartial* partials; // one entry
+};
+hipError_t launch_small_f64(const SmallArgs& a, hipStream_t s);
+
+// One layer in FP32 or FP64 (operand = X itself, ping-pong buffers).
+struct WideArgs {
+    int64_t np, n;
+    const void* X_in;       // full symmetric current X
+    void* X_out;            // full symmetric next X (or unused on the last layer)
+    void* A;                // accumulator, upper triangle
+    double a, b, c, d_next;
+    int last, out_mode, entropy;
+    void* D;
+    int64_t ldd;
+    const Params* P;
+    TracePartial* partials;
+};
+hipError_t launch_layer_f32(const WideArgs& a, hipStream_t s);
+hipError_t launch_layer_f64(const WideArgs& a, hipStream_t s);
+
+// Deterministic reduction of tile partials: out_tr = sum tr, out_sq = sum sq; if entropy,
+// out_S = 4 ln2 (sum tr - sum sq).
+hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,
+                                  double* out_sq, double* out_S, const Params* P, hipStream_t s);
+
+}  // namespace fe

@@ -1,0 +1,202 @@
+"""GPU parity: fe_expand_density / fe_rescale through the C ABI against the CPU oracle.
+
+Tolerances:
+  * FP64 mode vs the oracle recursion with the same coefficients: max |dD| <= 1e-11
+    (rounding of ~L dense FP64 products with entries O(1)).
+  * 16-bit split modes: ||dD||_F / N <= 1e-5 against both the oracle recursion and the exact
+    density matrix (the accuracy bar of the expansion); D must be exactly symmetric.
+  * Every result prints ||dD||_F/N, max |dD| and |dTr D| against the exact definition.
+"""
+import numpy as np
+import pytest
+
+from oracle import fermi as F
+from oracle import recursion as R
+from paper_2605_08523_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_08523_amd import api as _api
+    _api.lib()
+    return _api
+
+
+def report(tag, D, Dref, trD=None, trref=None):
+    n = D.shape[0]
+    fro = np.linalg.norm(D - Dref) / n
+    mx = np.max(np.abs(D - Dref))
+    msg = f"[{tag}] N={n} |dD|_F/N={fro:.3e} max|dD|={mx:.3e}"
+    if trD is not None:
+        msg += f" |dTrD|={abs(trD - trref):.3e}"
+    print(msg, flush=True)
+    return fro, mx
+
+
+def run(api, H, mu, kT, model, prec, **kw):
+    Hd = torch.from_numpy(np.ascontiguousarray(H)).cuda()
+    D, tr, tr2, info = api.expand_density(Hd, mu, kT, model, prec=prec, want_info=True, **kw)
+    torch.cuda.synchronize()
+    return D.double().cpu().numpy(), float(tr), float(tr2), info, D
+
+
+def test_small_dense_fp64(api, paper_model):
+    m = paper_model
+    c = W.config_small_dense(0)
+    H = c["H"]
+    mu = F.mu_for_filling(np.linalg.eigvalsh(H), c["n_target"], c["kT"])
+    print(f"case small_dense_fp64 mu={mu}", flush=True)
+    D, tr, tr2, info, Dt = run(api, H, mu, c["kT"], m, "fp64", out_dtype=torch.float64)
+    Drec, oinfo = R.mlsp2_density(H, mu, c["kT"], m.theta, m.beta0, m.mu0)
+    exact = F.density(H, mu, c["kT"])
+    report("fp64 vs recursion", D, Drec)
+    fro, _ = report("fp64 vs exact", D, exact["D"], tr, exact["trD"])
+    assert np.max(np.abs(D - Drec)) <= 1e-11
+    assert fro <= 1e-9
+    assert info["flipped"] == int(oinfo["flipped"]) and info["clamped"] == 0
+    assert info["beta_p"] == pytest.approx(oinfo["beta_p"], rel=1e-13)
+    assert tr == pytest.approx(np.trace(Drec), abs=1e-10)
+    assert tr2 == pytest.approx(np.sum(Drec * Drec), abs=1e-10)
+    assert torch.equal(Dt, Dt.T)
+
+
+CASES = [
+    ("dense128", lambda: (W.random_dense(128, 0), 0.045, 0.1)),
+    ("dense200_noflip", lambda: (W.random_dense(200, 5), -0.3, 0.08)),
+    ("dense384", lambda: (W.random_dense(384, 6), 0.2, 0.05)),
+    ("anderson512", lambda: (W.anderson_cubic(8, 7), 0.0, 0.05)),
+    ("dense1000", lambda: (W.random_dense(1000, 8), 0.1, 0.1)),
+    ("banded700", lambda: (W.banded_decay(700, 8.0, 2.0, 9), 0.3, 0.2)),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_split_modes_against_oracle(api, paper_model, prec, name, make):
+    m = paper_model
+    H, mu, kT = make()
+    print(f"case {name} {prec}", flush=True)
+    D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec)
+    Drec, oinfo = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
+    exact = F.density(H, mu, kT)
+    fro_r, _ = report(f"{name} {prec} vs recursion", D, Drec)
+    fro_e, _ = report(f"{name} {prec} vs exact", D, exact["D"], tr, exact["trD"])
+    assert torch.equal(Dt, Dt.T), "D must be exactly symmetric"
+    assert fro_r <= 1e-5 and fro_e <= 1e-5
+    assert info["flipped"] == int(oinfo["flipped"])
+    # the kernel's FP64 traces agree with the trace of the matrix it wrote
+    assert tr == pytest.approx(np.trace(D), abs=1e-9 * H.shape[0])
+    assert tr2 == pytest.approx(np.sum(D * D), abs=1e-9 * H.shape[0])
+
+
+def test_anderson_4096_fp16x2(api, paper_model):
+    """The benchmark workload at full size, in the launch configuration the benchmark times."""
+    m = paper_model
+    c = W.config_anderson_4096()
+    print("case anderson4096 fp16x2", flush=True)
+    D, tr, tr2, info, Dt = run(api, c["H"], c["mu"], c["kT"], m, "fp16x2")
+    assert info["rc"] == 0 and info["beta_p"] == pytest.approx(280.0, rel=0.01)
+    exact = F.density(c["H"], c["mu"], c["kT"])
+    fro, _ = report("anderson4096 fp16x2 vs exact", D, exact["D"], tr, exact["trD"])
+    assert fro <= 1e-5
+    assert torch.equal(Dt, Dt.T)
+
+
+def test_strided_inputs_and_fp64_output(api, paper_model):
+    m = paper_model
+    H = W.random_dense(300, 12)
+    big = np.zeros((300, 320))
+    big[:, :300] = H
+    Hd = torch.from_numpy(big).cuda()[:, :300]
+    full = torch.full((300, 310), 7.0, dtype=torch.float64, device="cuda")
+    out = full[:, :300]
+    D, tr, tr2, info = api.expand_density(Hd, 0.1, 0.1, m, prec="fp16x2", out=out, want_info=True)
+    torch.cuda.synchronize()
+    Dn = out.cpu().numpy()
+    Drec, _ = R.mlsp2_density(H, 0.1, 0.1, m.theta, m.beta0, m.mu0)
+    fro, _ = report("strided fp64-out", Dn, Drec)
+    assert fro <= 1e-5
+    assert torch.all(full[:, 300:] == 7.0)      # padding columns of the output untouched
+
+
+def test_clamp_warning(api, paper_model):
+    m = paper_model
+    H = W.random_dense(160, 13)
+    lo, hi = F.gershgorin(H)
+    kT = (hi - lo) / 3000.0
+    D, tr, tr2, info, _ = run(api, H, 0.0, kT, m, "fp16x2")
+    assert info["rc"] == api.FE_WARN_BETA_CLAMPED and info["clamped"] == 1
+    Drec, oinfo = R.mlsp2_density(H, 0.0, kT, m.theta, m.beta0, m.mu0)
+    assert oinfo["clamped"]
+    assert info["beta_p"] == pytest.approx(oinfo["beta_p"], rel=1e-12)
+    fro, _ = report("clamped", D, Drec)
+    assert fro <= 1e-5
+
+
+def test_domain_and_nonfinite_errors(api, paper_model):
+    m = paper_model
+    H = W.random_dense(64, 14)
+    lo, hi = F.gershgorin(H)
+    Hd = torch.from_numpy(H).cuda()
+    with pytest.raises(api.FeError) as e:
+        api.expand_density(Hd, hi + 1.0, 0.1, m, prec="fp16x2", want_info=True)
+    assert e.value.code == api.FE_ERR_DOMAIN
+    D, _, _, _ = api.expand_density(Hd, hi + 1.0, 0.1, m, prec="fp16x2")
+    torch.cuda.synchronize()
+    assert torch.isnan(D).all(), "a domain error must not produce numbers"
+    H2 = H.copy()
+    H2[3, 5] = H2[5, 3] = np.nan
+    with pytest.raises(api.FeError) as e:
+        api.expand_density(torch.from_numpy(H2).cuda(), 0.0, 0.1, m, prec="fp16x2", want_info=True)
+    assert e.value.code == api.FE_ERR_NONFINITE
+    with pytest.raises(api.FeError) as e:
+        api.expand_density(Hd, 0.0, -0.1, m, prec="fp16x2")
+    assert e.value.code == api.FE_ERR_DOMAIN
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+def test_degenerate_identity(api, paper_model, prec):
+    m = paper_model
+    H = 0.2 * np.eye(96)
+    D, tr, _, info, _ = run(api, H, 0.25, 0.05, m, prec)
+    assert info["degenerate"] == 1
+    f = F.fermi(np.array([0.2]), 0.25, 0.05)[0]
+    # every eigenvalue sits on the steep part of the step (slope ~ beta0/4 in the model
+    # coordinate), where FP32-level rounding is amplified; the FP64 path stays at model error
+    tol = 1e-7 if prec == "fp64" else 5e-5
+    np.testing.assert_allclose(D, f * np.eye(96), atol=tol)
+    assert np.linalg.norm(D - f * np.eye(96)) / 96 <= 1e-5
+
+
+def test_rescale_parity(api, paper_model):
+    m = paper_model
+    for mu in (-0.4, 0.3):
+        H = W.random_dense(257, 15)
+        X0, info = api.rescale(torch.from_numpy(H).cuda(), mu, 0.07, m)
+        Xref, oinfo = R.rescale(H, mu, 0.07, m.beta0, m.mu0)
+        np.testing.assert_allclose(X0.cpu().numpy(), Xref, atol=2e-7, rtol=0)
+        for k in ("emin", "emax", "mu_p", "beta_p", "beta_max", "scale", "shift"):
+            assert info[k] == pytest.approx(oinfo[k], rel=1e-13, abs=1e-15), k
+        assert info["flipped"] == int(oinfo["flipped"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+def test_entropy_against_oracle(api, paper_model, prec):
+    m = paper_model
+    alpha = 0.842704
+    H = W.random_dense(128 if prec == "fp64" else 500, 16)
+    mu, kT = 0.05, 0.1
+    S, info = api.expand_entropy(torch.from_numpy(H).cuda(), mu, kT, m, alpha, prec=prec, want_info=True)
+    S = float(S)
+    Srec, _ = R.entropy_expansion(H, mu, kT, m.theta, m.beta0, m.mu0, alpha)
+    Sex = F.entropy(H, mu, kT)
+    print(f"[entropy {prec}] S={S:.10f} S_rec={Srec:.10f} S_exact={Sex:.10f} "
+          f"rel(rec)={abs(S - Srec) / Srec:.3e} rel(exact)={abs(S - Sex) / Sex:.3e}", flush=True)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert abs(S - Srec) <= tol * abs(Srec)
