@@ -10,7 +10,6 @@
 #include "fe_internal.h"
 
 namespace fe {
-int split_tile_ok(int tile);
 int small_f64_max_np();
 }  // namespace fe
 
@@ -23,6 +22,11 @@ struct fe_workspace {
     fe::Params* params = nullptr;                 // [2]
     fe::BoundsPartial* bparts = nullptr;          // [2][kMaxBoundsBlocks]
     fe::TracePartial* tparts = nullptr;           // [2][kMaxTiles]
+    int n_cu = 0;                                 // compute units of the device
+    float* sk_partial = nullptr;                  // stream-K partial tiles [2][n_cu][256*256]
+    uint32_t* sk_flags = nullptr;                 // stream-K flags [n_cu]
+    int* sk_err = nullptr;                        // stream-K wait failure flag
+    uint32_t epoch = 0;                           // last stream-K launch epoch
 };
 
 namespace {
@@ -91,19 +95,30 @@ int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, 
     return FE_OK;
 }
 
-int select_tile(int64_t n) {
-    const char* env = getenv("FE_TILE");
-    if (env) {
-        int t = atoi(env);
-        if (fe::split_tile_ok(t)) return t;
-    }
-    return n > 8192 ? 256 : 128;
+constexpr int64_t kStreamKMinN = 1536;   // workspaces for n >= this carry stream-K buffers
+
+// Schedule of the split-precision layer kernel: data-parallel by default (measured faster at
+// N = 4096 so far); FE_SCHEDULE=sk selects the persistent stream-K schedule, FE_SCHEDULE=dp the
+// data-parallel one.
+int use_streamk(int64_t n, const fe_workspace* ws) {
+    if (!ws->sk_partial) return 0;
+    const char* env = getenv("FE_SCHEDULE");
+    (void)n;
+    return env && env[0] == 's';
 }
 
 int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
     FE_HIP(hipStreamSynchronize(s));
     fe::Params p;
     FE_HIP(hipMemcpy(&p, ws->params + which, sizeof(p), hipMemcpyDeviceToHost));
+    if (ws->sk_err) {
+        int err = 0;
+        FE_HIP(hipMemcpy(&err, ws->sk_err, sizeof(int), hipMemcpyDeviceToHost));
+        if (err) {
+            FE_HIP(hipMemset(ws->sk_err, 0, sizeof(int)));
+            return fail(FE_ERR_HIP, "a stream-K workgroup gave up waiting for a partial tile");
+        }
+    }
     info->emin = p.emin;
     info->emax = p.emax;
     info->mu_p = p.mu_p;
@@ -198,7 +213,14 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         sa.P = P; sa.partials = tp;
         FE_HIP(fe::launch_small_f64(sa, s));
     } else if (split) {
-        const int tile = select_tile(n);
+        fe::SplitPlan plan{};
+        plan.streamk = use_streamk(n, ws);
+        plan.grid = ws->n_cu;
+        plan.partial = ws->sk_partial;
+        plan.own = ws->sk_partial ? ws->sk_partial + (size_t)ws->n_cu * 256 * 256 : nullptr;
+        plan.flags = ws->sk_flags;
+        plan.err = ws->sk_err;
+        const int tile = fe::split_tile_for(plan.streamk);
         const int64_t np = round_up(n, tile);
         if (np > ws->np_cap) return fail(FE_ERR_WORKSPACE, "padded size exceeds the workspace");
         SplitBufs b = carve_split(ws->slot[which], np);
@@ -223,7 +245,11 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             la.last = (i + 1 == m->L);
             la.out_mode = out_mode; la.entropy = entropy; la.D = D; la.ldd = ldd;
             la.P = P; la.partials = tp;
-            FE_HIP(fe::launch_layer_split(la, bf, tile, s));
+            if (plan.streamk) {
+                if (++ws->epoch == 0) ++ws->epoch;   // flags start at 0: never reuse 0
+                plan.epoch = ws->epoch;
+            }
+            FE_HIP(fe::launch_layer_split(la, bf, plan, s));
         }
     } else {
         return fail(FE_ERR_ARG, "precision mode not available for this size in this build");
@@ -258,6 +284,14 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
         e = hipMalloc(reinterpret_cast<void**>(&ws->bparts), 2 * fe::kMaxBoundsBlocks * sizeof(fe::BoundsPartial));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void**>(&ws->tparts), 2 * (size_t)fe::kMaxTiles * sizeof(fe::TracePartial));
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ws->n_cu, hipDeviceAttributeMultiprocessorCount, ws->device);
+    if (e == hipSuccess && max_n >= kStreamKMinN) {
+        e = hipMalloc(reinterpret_cast<void**>(&ws->sk_partial), 2 * (size_t)ws->n_cu * 256 * 256 * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_flags), (size_t)ws->n_cu * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(ws->sk_flags, 0, (size_t)ws->n_cu * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_err), sizeof(int));
+        if (e == hipSuccess) e = hipMemset(ws->sk_err, 0, sizeof(int));
+    }
     if (e != hipSuccess) {
         fe_workspace_destroy(ws);
         return hip_fail(e, "hipMalloc (workspace)");
@@ -273,6 +307,9 @@ int fe_workspace_destroy(fe_workspace* ws) {
     if (ws->params) (void)hipFree(ws->params);
     if (ws->bparts) (void)hipFree(ws->bparts);
     if (ws->tparts) (void)hipFree(ws->tparts);
+    if (ws->sk_partial) (void)hipFree(ws->sk_partial);
+    if (ws->sk_flags) (void)hipFree(ws->sk_flags);
+    if (ws->sk_err) (void)hipFree(ws->sk_err);
     delete ws;
     return FE_OK;
 }

@@ -88,7 +88,18 @@ struct LayerArgs {
     const Params* P;        // flip flag for the last layer
     TracePartial* partials; // one per tile on the last layer
 };
-hipError_t launch_layer_split(const LayerArgs& a, int bf16, int tile, hipStream_t s);
+// Schedule of the split-precision layer kernel.
+struct SplitPlan {
+    int streamk;          // 0: one workgroup per 128 x 128 upper tile; 1: persistent stream-K
+    int grid;             // stream-K workgroups (one per CU)
+    float* partial;       // stream-K published partial tiles, grid x 256 x 256 floats
+    float* own;           // stream-K per-workgroup staging of finished tiles, grid x 256 x 256 floats
+    uint32_t* flags;      // stream-K publication flags, one per workgroup (zero-initialised)
+    uint32_t epoch;       // value written to a flag by this launch (distinct per launch)
+    int* err;             // set to 1 if a bounded wait gave up
+};
+int split_tile_for(int streamk);
+hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s);
 
 // Whole recursion for np <= 128 in FP64 inside one workgroup's LDS. The coefficients travel
 // by value with the launch.
