@@ -119,6 +119,45 @@ int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double
                       const fe_model* mS, double alpha, int32_t prec, double* S,
                       fe_rescale_info* info, fe_workspace* ws, void* stream);
 
+/* ---- batches of matrices of uneven size ------------------------------------------------ */
+
+/* One Hamiltonian of a batch. All pointers are device memory owned by the caller. */
+typedef struct {
+    const double* H;      /* n x n, leading dimension ldh >= n */
+    int64_t n, ldh;
+    double mu, kT;        /* chemical potential and temperature of this matrix */
+    void* D;              /* n x n density matrix (ld ldd) or NULL for traces only */
+    int64_t ldd;
+    int32_t d_is_fp64;    /* D is float64 (else float32) */
+    double* trD;          /* Tr D or NULL */
+    double* trD2;         /* sum_ij D_ij^2 or NULL */
+    double* S;            /* entropy or NULL (needs an entropy model) */
+} fe_batch_item;
+
+typedef struct fe_batch_plan fe_batch_plan;
+
+/* Alg. 2 for every item of a batch (a batch of independent problems; the method is the same as
+ * for one matrix). The plan lays the batch out in the workspace (which must have been created
+ * with max_batch >= count and batch_elems >= sum of padded sizes squared, padding to multiples
+ * of 128), uploads the descriptors (synchronously) and captures the launch sequence into a HIP
+ * graph: batched bounds and rescale, one grouped launch per layer over all upper tiles of all
+ * matrices, per-matrix traces, then the entropy pass if mS is not NULL (mS must share beta0 and
+ * mu0 with m). Precision: FE_PREC_FP16X2 or FE_PREC_BF16X2. status: device int32[count] or NULL,
+ * receives each item's rescale status (FE_OK, FE_WARN_BETA_CLAMPED, FE_ERR_DOMAIN,
+ * FE_ERR_NONFINITE); items with an error get NaN outputs. A workspace holds one batch layout: a
+ * new plan makes earlier plans on it stale (their launch returns FE_ERR_WORKSPACE). The items'
+ * pointers are captured; launching replays the graph on `stream` (asynchronous). */
+int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_model* m,
+                         const fe_model* mS, double alpha, int32_t prec, int32_t* status,
+                         fe_workspace* ws, fe_batch_plan** plan);
+int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
+int fe_batch_plan_destroy(fe_batch_plan* plan);
+
+/* One-shot batch: create a plan, launch it on `stream`, wait for the stream, destroy the plan. */
+int fe_batched_expand(const fe_batch_item* items, int32_t count, const fe_model* m,
+                      const fe_model* mS, double alpha, int32_t prec, int32_t* status,
+                      fe_workspace* ws, void* stream);
+
 /* ---- helpers ---------------------------------------------------------------------------- */
 
 /* SP2 for a known chemical potential embedded in the layer form (Eq. sp2-mu; App. C):

@@ -252,3 +252,80 @@ def layer_count(beta_p: float) -> float:
 
 def version() -> str:
     return lib().fe_version().decode()
+
+
+# ---- batches -----------------------------------------------------------------------------
+
+class fe_batch_item(C.Structure):
+    _fields_ = [("H", C.c_void_p), ("n", C.c_int64), ("ldh", C.c_int64), ("mu", C.c_double),
+                ("kT", C.c_double), ("D", C.c_void_p), ("ldd", C.c_int64),
+                ("d_is_fp64", C.c_int32), ("trD", C.c_void_p), ("trD2", C.c_void_p),
+                ("S", C.c_void_p)]
+
+
+SIGNATURES.update({
+    "fe_batch_plan_create": (_I32, [C.POINTER(fe_batch_item), _I32, C.POINTER(fe_model),
+                                    C.POINTER(fe_model), _D, _I32, _P, _P, C.POINTER(_P)]),
+    "fe_batch_plan_launch": (_I32, [_P, _P]),
+    "fe_batch_plan_destroy": (_I32, [_P]),
+    "fe_batched_expand": (_I32, [C.POINTER(fe_batch_item), _I32, C.POINTER(fe_model),
+                                 C.POINTER(fe_model), _D, _I32, _P, _P, _P]),
+})
+
+
+class BatchPlan:
+    """A captured batch (fe_batch_plan_create): `launch()` replays it on the current stream.
+
+    Each entry of `mats` is a dict with keys H (float64 device tensor), mu, kT. Outputs are
+    allocated here: D (float32, or float64 with d_dtype), traces tr[b] = (Tr D, sum D_ij^2), S[b]
+    (entropy, when model_s is given) and status[b] (int32 rescale status)."""
+
+    def __init__(self, mats, model, prec="fp16x2", model_s=None, alpha=1.0, ws=None,
+                 want_D=True, d_dtype=None):
+        import torch
+        self.count = len(mats)
+        dev = mats[0]["H"].device
+        d_dtype = d_dtype or torch.float32
+        self.H = [m["H"] for m in mats]
+        self.D = []
+        self.tr = torch.zeros((self.count, 2), dtype=torch.float64, device=dev)
+        self.S = torch.zeros(self.count, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        arr = (fe_batch_item * self.count)()
+        elems = 0
+        for b, m in enumerate(mats):
+            n, ldh = _check_H(m["H"])
+            D = torch.empty((n, n), dtype=d_dtype, device=dev) if want_D else None
+            self.D.append(D)
+            arr[b] = fe_batch_item(m["H"].data_ptr(), n, ldh, float(m["mu"]), float(m["kT"]),
+                                   D.data_ptr() if want_D else None, n if want_D else 0,
+                                   int(d_dtype == torch.float64),
+                                   self.tr.data_ptr() + 16 * b, self.tr.data_ptr() + 16 * b + 8,
+                                   self.S.data_ptr() + 8 * b if model_s is not None else None)
+            np_ = -(-n // 128) * 128
+            elems += np_ * np_
+        self._items = arr
+        self.ws = ws or Workspace(128, max_batch=self.count, batch_elems=elems)
+        self._m = _model_of(model)
+        self._ms = _model_of(model_s) if model_s is not None else None
+        p = C.c_void_p()
+        _check(lib().fe_batch_plan_create(arr, self.count, C.byref(self._m.struct),
+                                          C.byref(self._ms.struct) if self._ms else None,
+                                          float(alpha), PREC[prec],
+                                          C.c_void_p(self.status.data_ptr()), self.ws.handle,
+                                          C.byref(p)))
+        self._p = p
+
+    def launch(self):
+        _check(lib().fe_batch_plan_launch(self._p, _stream_ptr()))
+
+    def close(self):
+        if self._p:
+            lib().fe_batch_plan_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,76 +13,11 @@ namespace fe {
 int small_f64_max_np();
 }  // namespace fe
 
-struct fe_workspace {
-    int device = 0;
-    int64_t max_n = 0;
-    int64_t np_cap = 0;           // largest padded size a single-matrix call may use
-    size_t slot_bytes = 0;
-    void* slot[2] = {nullptr, nullptr};           // 0: density, 1: entropy
-    fe::Params* params = nullptr;                 // [2]
-    fe::BoundsPartial* bparts = nullptr;          // [2][kMaxBoundsBlocks]
-    fe::TracePartial* tparts = nullptr;           // [2][kMaxTiles]
-    int n_cu = 0;                                 // compute units of the device
-    float* sk_partial = nullptr;                  // stream-K partial tiles [2][n_cu][256*256]
-    uint32_t* sk_flags = nullptr;                 // stream-K flags [n_cu]
-    int* sk_err = nullptr;                        // stream-K wait failure flag
-    uint32_t epoch = 0;                           // last stream-K launch epoch
-};
+#include "fe_host.h"
+
+using namespace fehost;
 
 namespace {
-
-thread_local std::string g_err = "no error";
-
-int fail(int code, const std::string& msg) {
-    g_err = msg;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what) {
-    return fail(FE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define FE_HIP(call)                                         \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
-    } while (0)
-
-constexpr int kMaxLayers = 4096;
-constexpr double kDSkip = 1e-8;   // accumulator weights below this are skipped (Sec. V.A)
-
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
-int check_model(const fe_model* m, const char* name) {
-    if (!m) return fail(FE_ERR_ARG, std::string(name) + " is NULL");
-    if (m->L < 1 || m->L > kMaxLayers) return fail(FE_ERR_ARG, std::string(name) + ": L out of range");
-    if (!m->theta) return fail(FE_ERR_ARG, std::string(name) + ": theta is NULL");
-    if (!(m->beta0 > 0.0) || !isfinite(m->beta0))
-        return fail(FE_ERR_ARG, std::string(name) + ": beta0 must be positive");
-    if (!(m->mu0 > 0.0 && m->mu0 < 1.0)) return fail(FE_ERR_ARG, std::string(name) + ": mu0 must lie in (0, 1)");
-    for (int i = 0; i < 4 * m->L; ++i)
-        if (!isfinite(m->theta[i])) return fail(FE_ERR_ARG, std::string(name) + ": non-finite coefficient");
-    return FE_OK;
-}
-
-// Largest |x_i| over the layers for model inputs in [0, 1] (after the entropy rescale when
-// alpha != 1): the 16-bit operands must stay well inside the FP16 range (hi is scaled by 2^11
-// inside the product).
-double layer_range(const fe_model* m, double alpha) {
-    double mx = 0.0;
-    const int kPts = 1025;
-    for (int k = 0; k < kPts; ++k) {
-        double y = (double)k / (kPts - 1);
-        double x = alpha * (y - m->mu0) + m->mu0;
-        mx = fmax(mx, fabs(x));
-        for (int i = 0; i < m->L; ++i) {
-            const double* t = m->theta + 4 * i;
-            x = t[0] * x * x + t[1] * x + t[2];
-            mx = fmax(mx, fabs(x));
-        }
-    }
-    return mx;
-}
 
 int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, fe_workspace* ws) {
     if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
@@ -263,7 +198,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
 
 extern "C" {
 
-const char* fe_last_error(void) { return g_err.c_str(); }
+const char* fe_last_error(void) { return last_error().c_str(); }
 
 const char* fe_version(void) { return "fe-mi355x 0.1 (gfx950)"; }
 
@@ -292,6 +227,17 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_err), sizeof(int));
         if (e == hipSuccess) e = hipMemset(ws->sk_err, 0, sizeof(int));
     }
+    if (e == hipSuccess && max_batch > 0) {
+        ws->max_batch = max_batch;
+        ws->batch_elems = batch_elems;
+        const int64_t bt = fe::batch_tile();
+        ws->batch_tiles = batch_elems / (bt * bt) + max_batch;
+        e = hipMalloc(&ws->arena, (size_t)batch_elems * 16);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->bmats), (size_t)max_batch * sizeof(fe::BatchMat));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->bparams), (size_t)max_batch * sizeof(fe::Params));
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void**>(&ws->btparts), (size_t)ws->batch_tiles * sizeof(fe::TracePartial));
+    }
     if (e != hipSuccess) {
         fe_workspace_destroy(ws);
         return hip_fail(e, "hipMalloc (workspace)");
@@ -310,6 +256,10 @@ int fe_workspace_destroy(fe_workspace* ws) {
     if (ws->sk_partial) (void)hipFree(ws->sk_partial);
     if (ws->sk_flags) (void)hipFree(ws->sk_flags);
     if (ws->sk_err) (void)hipFree(ws->sk_err);
+    if (ws->arena) (void)hipFree(ws->arena);
+    if (ws->bmats) (void)hipFree(ws->bmats);
+    if (ws->bparams) (void)hipFree(ws->bparams);
+    if (ws->btparts) (void)hipFree(ws->btparts);
     delete ws;
     return FE_OK;
 }

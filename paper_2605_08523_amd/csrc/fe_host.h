@@ -1,0 +1,96 @@
+// Host-side state and helpers shared by the C ABI translation units.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "fe_internal.h"
+
+struct fe_workspace {
+    int device = 0;
+    int64_t max_n = 0;
+    int64_t np_cap = 0;           // largest padded size a single-matrix call may use
+    size_t slot_bytes = 0;
+    void* slot[2] = {nullptr, nullptr};           // 0: density, 1: entropy
+    fe::Params* params = nullptr;                 // [2]
+    fe::BoundsPartial* bparts = nullptr;          // [2][kMaxBoundsBlocks]
+    fe::TracePartial* tparts = nullptr;           // [2][kMaxTiles]
+    int n_cu = 0;                                 // compute units of the device
+    float* sk_partial = nullptr;                  // stream-K partial tiles [2][n_cu][256*256]
+    uint32_t* sk_flags = nullptr;                 // stream-K flags [n_cu]
+    int* sk_err = nullptr;                        // stream-K wait failure flag
+    uint32_t epoch = 0;                           // last stream-K launch epoch
+    // batch capacity
+    int32_t max_batch = 0;
+    int64_t batch_elems = 0;                      // sum of padded sizes squared it can hold
+    int64_t batch_tiles = 0;                      // tile-trace slots
+    void* arena = nullptr;                        // 16 bytes per element (X, A, hi[2], lo[2])
+    fe::BatchMat* bmats = nullptr;                // [max_batch]
+    fe::Params* bparams = nullptr;                // [max_batch]
+    fe::TracePartial* btparts = nullptr;          // [batch_tiles]
+    uint64_t batch_gen = 0;                       // bumped by every batch plan created
+};
+
+namespace fehost {
+
+// Message of the last error on this thread (one instance for the whole library).
+inline std::string& last_error() {
+    thread_local std::string msg = "no error";
+    return msg;
+}
+
+inline int fail(int code, const std::string& msg) {
+    last_error() = msg;
+    return code;
+}
+
+inline int hip_fail(hipError_t e, const char* what) {
+    return fail(FE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FE_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+    } while (0)
+
+inline constexpr int kMaxLayers = 4096;
+inline constexpr double kDSkip = 1e-8;   // accumulator weights below this are skipped (Sec. V.A)
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+inline int check_model(const fe_model* m, const char* name) {
+    if (!m) return fail(FE_ERR_ARG, std::string(name) + " is NULL");
+    if (m->L < 1 || m->L > kMaxLayers) return fail(FE_ERR_ARG, std::string(name) + ": L out of range");
+    if (!m->theta) return fail(FE_ERR_ARG, std::string(name) + ": theta is NULL");
+    if (!(m->beta0 > 0.0) || !isfinite(m->beta0))
+        return fail(FE_ERR_ARG, std::string(name) + ": beta0 must be positive");
+    if (!(m->mu0 > 0.0 && m->mu0 < 1.0)) return fail(FE_ERR_ARG, std::string(name) + ": mu0 must lie in (0, 1)");
+    for (int i = 0; i < 4 * m->L; ++i)
+        if (!isfinite(m->theta[i])) return fail(FE_ERR_ARG, std::string(name) + ": non-finite coefficient");
+    return FE_OK;
+}
+
+// Largest |x_i| over the layers for model inputs in [0, 1] (after the entropy rescale when
+// alpha != 1): the 16-bit operands must stay well inside the FP16 range (hi is scaled by 2^11
+// inside the product).
+inline double layer_range(const fe_model* m, double alpha) {
+    double mx = 0.0;
+    const int kPts = 1025;
+    for (int k = 0; k < kPts; ++k) {
+        double y = (double)k / (kPts - 1);
+        double x = alpha * (y - m->mu0) + m->mu0;
+        mx = fmax(mx, fabs(x));
+        for (int i = 0; i < m->L; ++i) {
+            const double* t = m->theta + 4 * i;
+            x = t[0] * x * x + t[1] * x + t[2];
+            mx = fmax(mx, fabs(x));
+        }
+    }
+    return mx;
+}
+
+
+}  // namespace fehost

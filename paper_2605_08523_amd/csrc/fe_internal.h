@@ -135,6 +135,44 @@ struct WideArgs {
 hipError_t launch_layer_f32(const WideArgs& a, hipStream_t s);
 hipError_t launch_layer_f64(const WideArgs& a, hipStream_t s);
 
+// ---- batches of matrices of uneven size --------------------------------------------------
+// One matrix of a batch on the device (padded to a multiple of the 128-row tile).
+struct BatchMat {
+    const double* H;
+    int64_t n, ldh, np;
+    double mu, kT;
+    float* X;
+    float* A;
+    uint16_t* hi[2];
+    uint16_t* lo[2];
+    void* D;
+    int64_t ldd;
+    int32_t d_is_fp64;
+    int32_t item;           // index of the caller's item (status slot)
+    double* trD;
+    double* trD2;
+    double* S;
+    int32_t tile0;          // first tile of this matrix in the grouped grid
+    int32_t pad;
+};
+struct BatchLayerArgs {
+    const BatchMat* mats;
+    int count;
+    int parity;             // hi/lo buffer read by this layer
+    float a, b, c, d_next;
+    int last, entropy;
+    const Params* P;
+    TracePartial* partials;
+};
+int batch_tile();
+hipError_t launch_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P,
+                               hipStream_t s);
+hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
+                                double alpha, double mu0, double d0, int bf16, hipStream_t s);
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16, hipStream_t s);
+hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
+                               const Params* P, int entropy, int32_t* status, hipStream_t s);
+
 // Deterministic reduction of tile partials: out_tr = sum tr, out_sq = sum sq; if entropy,
 // out_S = 4 ln2 (sum tr - sum sq).
 hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,

@@ -1,0 +1,263 @@
+// Batched expansion of many Hamiltonians of uneven size (Alg. 2 applied to each matrix of a
+// batch): batched Gershgorin bounds and rescale parameters, batched rescale/split, one grouped
+// launch per layer covering every upper tile of every matrix, and per-matrix trace reductions.
+// Matrices are padded to multiples of 128; zero padding keeps the padded block decoupled
+// (X stays block diagonal) and the padding is masked out of D and the traces.
+#include <math.h>
+
+#include "split_common.h"
+
+namespace fe {
+namespace {
+
+using namespace split;
+using CfgB = Cfg<128, 2, 2, 32, 64, 1>;
+
+__device__ inline double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wmin(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wmax(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One workgroup per matrix: Gershgorin bounds (one wave per row) and the rescale parameters of
+// Sec. IV.1, as in the single-matrix prologue.
+__global__ void __launch_bounds__(256)
+k_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P) {
+    const int b = blockIdx.x;
+    if (b >= count) return;
+    const BatchMat m = mats[b];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double lo = INFINITY, hi = -INFINITY;
+    int bad = 0;
+    for (int64_t i = wave; i < m.n; i += 4) {
+        const double* row = m.H + i * m.ldh;
+        double s = 0.0;
+        for (int64_t j = lane; j < m.n; j += 64) s += fabs(row[j]);
+        s = wsum(s);
+        const double d = row[i];
+        if (!isfinite(s)) bad = 1;
+        lo = fmin(lo, d - (s - fabs(d)));
+        hi = fmax(hi, d + (s - fabs(d)));
+    }
+    __shared__ double slo[4], shi[4];
+    __shared__ int sbad[4];
+    if (lane == 0) {
+        slo[wave] = lo;
+        shi[wave] = hi;
+        sbad[wave] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < 4; ++w) {
+        lo = fmin(lo, slo[w]);
+        hi = fmax(hi, shi[w]);
+        bad |= sbad[w];
+    }
+    const double mu = m.mu, kT = m.kT;
+    Params p;
+    p.emin = lo;
+    p.emax = hi;
+    p.flipped = p.clamped = p.degenerate = 0;
+    p.status = FE_OK;
+    const double width = hi - lo;
+    if (bad || !isfinite(lo) || !isfinite(hi)) {
+        p.status = FE_ERR_NONFINITE;
+        p.mu_p = p.beta_p = p.beta_max = p.scale = p.shift = NAN;
+    } else if (!(kT > 0.0)) {
+        p.status = FE_ERR_DOMAIN;
+        p.mu_p = p.beta_p = p.beta_max = p.scale = p.shift = NAN;
+    } else if (width <= 1e-300 * fmax(1.0, fabs(hi))) {
+        double y = mu0 + (mu - lo) / (kT * beta0);
+        p.degenerate = 1;
+        if (!(y >= 0.0 && y <= 1.0)) {
+            p.clamped = 1;
+            y = fmin(1.0, fmax(0.0, y));
+        }
+        p.mu_p = NAN;
+        p.beta_p = INFINITY;
+        p.beta_max = NAN;
+        p.scale = 0.0;
+        p.shift = y;
+    } else if (!(lo < mu && mu < hi)) {
+        p.status = FE_ERR_DOMAIN;
+        p.mu_p = p.beta_p = p.beta_max = p.scale = p.shift = NAN;
+    } else {
+        double mu_p = (hi - mu) / width;
+        double beta_p = width / kT;
+        const int flip = mu_p > 0.5;
+        if (flip) mu_p = 1.0 - mu_p;
+        const double bmax = fmin(mu0 / mu_p, (1.0 - mu0) / (1.0 - mu_p)) * beta0;
+        if (beta_p > bmax) {
+            beta_p = bmax;
+            p.clamped = 1;
+            p.status = FE_WARN_BETA_CLAMPED;
+        }
+        const double r = beta_p / beta0;
+        p.scale = flip ? r / width : -r / width;
+        p.shift = flip ? r * (-lo / width - mu_p) + mu0 : r * (hi / width - mu_p) + mu0;
+        p.mu_p = mu_p;
+        p.beta_p = beta_p;
+        p.beta_max = bmax;
+        p.flipped = flip;
+    }
+    P[b] = p;
+}
+
+// Rescale and split of every matrix: blockIdx.y selects the matrix, blockIdx.x a chunk.
+template <bool BF>
+__global__ void __launch_bounds__(256)
+k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, double mu0, float d0) {
+    const int b = blockIdx.y;
+    if (b >= count) return;
+    const BatchMat m = mats[b];
+    const double scale = P[b].scale, shift = P[b].shift;
+    const int64_t total = m.np * m.np;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / m.np, j = e - i * m.np;
+        double x = 0.0;
+        if (i < m.n && j < m.n) {
+            x = scale * m.H[i * m.ldh + j] + (i == j ? shift : 0.0);
+            x = alpha * x + (i == j ? (1.0 - alpha) * mu0 : 0.0);
+        }
+        const float xf = (float)x;
+        m.X[e] = xf;
+        m.A[e] = d0 * xf;
+        uint16_t h, l;
+        split16<BF>(xf, h, l);
+        m.hi[0][e] = h;
+        m.lo[0][e] = l;
+    }
+}
+
+// One layer for every upper tile of every matrix. Workgroup g finds its matrix by binary search
+// over the tile prefix sums (matrices sorted by decreasing size, so the longest K loops start
+// first), then runs the same K loop and fused epilogue as the single-matrix kernel.
+template <bool BF>
+__global__ void __launch_bounds__(CfgB::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_batch_layer(BatchLayerArgs q) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int g = blockIdx.x;
+    int lo = 0, hi = q.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (q.mats[mid].tile0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchMat& m = q.mats[lo];
+    const int t = g - m.tile0;
+    const int T = (int)(m.np / CfgB::BM);
+    int I, J;
+    tile_coords(t, T, I, J);
+    LayerArgs p;
+    p.np = m.np;
+    p.n = m.n;
+    p.hi_in = m.hi[q.parity];
+    p.lo_in = m.lo[q.parity];
+    p.hi_out = m.hi[q.parity ^ 1];
+    p.lo_out = m.lo[q.parity ^ 1];
+    p.X = m.X;
+    p.A = m.A;
+    p.a = q.a;
+    p.b = q.b;
+    p.c = q.c;
+    p.d_next = q.d_next;
+    p.last = q.last;
+    p.entropy = q.entropy;
+    p.D = m.D;
+    p.ldd = m.ldd;
+    p.out_mode = q.entropy ? 2 : (m.D ? (m.d_is_fp64 ? 1 : 0) : 2);
+    p.P = q.P + lo;
+    p.partials = q.partials + m.tile0;
+    Acc<CfgB> acc;
+#pragma unroll
+    for (int mb = 0; mb < CfgB::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < CfgB::NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc.v[mb][nb][j] = 0.0f;
+    kloop<BF, CfgB>(p.hi_in, p.lo_in, p.np, (int64_t)I * CfgB::BM, (int64_t)J * CfgB::BM, 0,
+                    (int)(p.np / CfgB::BK), acc, reinterpret_cast<uint16_t*>(smem));
+    epilogue<BF, CfgB>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
+}
+
+// Per-matrix fixed-order reduction of the tile traces into Tr, sum of squares, and S (entropy).
+__global__ void __launch_bounds__(64)
+k_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials, const Params* P,
+               int entropy, int32_t* status) {
+    const int b = blockIdx.x;
+    if (b >= count) return;
+    const BatchMat m = mats[b];
+    const int T = (int)(m.np / CfgB::BM);
+    const int nt = T * (T + 1) / 2;
+    double tr = 0.0, sq = 0.0;
+    for (int k = threadIdx.x; k < nt; k += 64) {
+        tr += partials[m.tile0 + k].tr;
+        sq += partials[m.tile0 + k].sq;
+    }
+    tr = wsum(tr);
+    sq = wsum(sq);
+    if (threadIdx.x == 0) {
+        const double bad = P[b].status < 0 ? NAN : 0.0;
+        if (entropy) {
+            if (m.S) *m.S = 4.0 * 0.69314718055994530942 * (tr - sq) + bad;
+        } else {
+            if (m.trD) *m.trD = tr + bad;
+            if (m.trD2) *m.trD2 = sq + bad;
+        }
+        if (status && (!entropy || P[b].status < 0)) status[m.item] = P[b].status;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_bounds, dim3(count), dim3(256), 0, s, mats, count, beta0, mu0, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
+                                double alpha, double mu0, double d0, int bf16, hipStream_t s) {
+    int chunks = (int)((max_np * max_np + 4095) / 4096);
+    if (chunks < 1) chunks = 1;
+    if (chunks > 64) chunks = 64;
+    dim3 grid(chunks, count);
+    if (bf16)
+        hipLaunchKernelGGL(k_batch_rescale<true>, grid, dim3(256), 0, s, mats, count, P, alpha, mu0, (float)d0);
+    else
+        hipLaunchKernelGGL(k_batch_rescale<false>, grid, dim3(256), 0, s, mats, count, P, alpha, mu0, (float)d0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16, hipStream_t s) {
+    static bool done[2] = {false, false};
+    auto kern = bf16 ? k_batch_layer<true> : k_batch_layer<false>;
+    if (!done[bf16]) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)CfgB::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        done[bf16] = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(total_tiles), dim3(CfgB::NT), CfgB::LDS_BYTES, s, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
+                               const Params* P, int entropy, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reduce, dim3(count), dim3(64), 0, s, mats, count, partials, P,
+                       entropy, status);
+    return hipGetLastError();
+}
+
+int batch_tile() { return CfgB::BM; }
+
+}  // namespace fe
