@@ -187,7 +187,35 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             FE_HIP(fe::launch_layer_split(la, bf, plan, s));
         }
     } else {
-        return fail(FE_ERR_ARG, "precision mode not available for this size in this build");
+        // FP64 beyond the one-workgroup size, or FP32: 64 x 64 tiled MFMA layers on X itself
+        const bool f64 = prec == FE_PREC_FP64;
+        const int tile = fe::wide_tile();
+        const int64_t np = round_up(n, tile);
+        if (np > ws->np_cap) return fail(FE_ERR_WORKSPACE, "padded size exceeds the workspace");
+        WideBufs b = carve_wide(ws->slot[which], np, f64 ? sizeof(double) : sizeof(float));
+        fe::RescaleArgs ra{};
+        ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = P;
+        ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
+        if (f64) {
+            ra.X64 = static_cast<double*>(b.X[0]); ra.A64 = static_cast<double*>(b.A); ra.mode = 2;
+        } else {
+            ra.X32 = static_cast<float*>(b.X[0]); ra.A32 = static_cast<float*>(b.A); ra.mode = 1;
+        }
+        FE_HIP(fe::launch_rescale(ra, s));
+        const int T = (int)(np / tile);
+        npart = T * (T + 1) / 2;
+        if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
+        for (int i = 0; i < m->L; ++i) {
+            fe::WideArgs wa{};
+            wa.np = np; wa.n = n;
+            wa.X_in = b.X[i & 1]; wa.X_out = b.X[(i + 1) & 1]; wa.A = b.A;
+            wa.a = th[4 * i]; wa.b = th[4 * i + 1]; wa.c = th[4 * i + 2];
+            wa.d_next = (i + 1 < m->L) ? dval(i + 1) : 0.0;
+            wa.last = (i + 1 == m->L);
+            wa.out_mode = out_mode; wa.entropy = entropy; wa.D = D; wa.ldd = ldd;
+            wa.P = P; wa.partials = tp;
+            FE_HIP(f64 ? fe::launch_layer_f64(wa, s) : fe::launch_layer_f32(wa, s));
+        }
     }
     FE_HIP(fe::launch_reduce_partials(tp, npart, trD, trD2, S, P, s));
     if (info) return read_info(ws, which, s, info);

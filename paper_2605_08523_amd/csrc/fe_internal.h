@@ -119,19 +119,26 @@ struct SmallArgs {
 };
 hipError_t launch_small_f64(const SmallArgs& a, hipStream_t s);
 
-// One layer in FP32 or FP64 (operand = X itself, ping-pong buffers).
+// FP32 / FP64 tiled MFMA kernels (64 x 64 tiles) in two forms:
+//  layer form (plain = 0): one layer of the recursion on X itself (operands = the full symmetric
+//    X_in, ping-pong with X_out), upper tiles only, fused epilogue as in the split kernel;
+//  product form (plain = 1): C = X_in B_in^T for row-major np x np operands over all tiles, written
+//    row-major to X_out (used by the trainer's backward pass, where B_in = X is symmetric).
 struct WideArgs {
     int64_t np, n;
-    const void* X_in;       // full symmetric current X
-    void* X_out;            // full symmetric next X (or unused on the last layer)
-    void* A;                // accumulator, upper triangle
+    const void* X_in;       // layer: full symmetric X; product: left operand
+    const void* B_in;       // product: right operand (rows)
+    void* X_out;            // layer: next X (full); product: C
+    void* A;                // accumulator, upper triangle (layer form)
     double a, b, c, d_next;
     int last, out_mode, entropy;
     void* D;
     int64_t ldd;
     const Params* P;
     TracePartial* partials;
+    int plain;
 };
+int wide_tile();
 hipError_t launch_layer_f32(const WideArgs& a, hipStream_t s);
 hipError_t launch_layer_f64(const WideArgs& a, hipStream_t s);
 

@@ -1,0 +1,55 @@
+"""GPU parity of the FP32 and FP64 tiled layer kernels (any N) against the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle import fermi as F
+from oracle import recursion as R
+from paper_2605_08523_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_08523_amd import api as _api
+    _api.lib()
+    return _api
+
+
+@pytest.mark.parametrize("prec,n,tol_max", [("fp64", 200, 1e-10), ("fp64", 700, 1e-10),
+                                            ("fp32", 130, None), ("fp32", 1000, None)])
+def test_wide_modes(api, paper_model, prec, n, tol_max):
+    m = paper_model
+    H = W.random_dense(n, 40 + n)
+    mu, kT = 0.05, 0.1
+    print(f"case wide {prec} N={n}", flush=True)
+    Hd = torch.from_numpy(H).cuda()
+    D, tr, tr2, info = api.expand_density(Hd, mu, kT, m, prec=prec, out_dtype=torch.float64,
+                                          want_info=True)
+    torch.cuda.synchronize()
+    Dg = D.cpu().numpy()
+    Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
+    exact = F.density(H, mu, kT)
+    fro = np.linalg.norm(Dg - Drec) / n
+    mx = np.max(np.abs(Dg - Drec))
+    print(f"[wide {prec} N={n}] |dD|_F/N={fro:.3e} max={mx:.3e} vs exact "
+          f"{np.linalg.norm(Dg - exact['D']) / n:.3e}", flush=True)
+    assert torch.equal(D, D.T)
+    if tol_max is not None:
+        assert mx <= tol_max
+    assert fro <= 1e-5
+    assert float(tr) == pytest.approx(np.trace(Dg), abs=1e-9 * n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_entropy(api, paper_model, prec):
+    m = paper_model
+    H = W.random_dense(333, 41)
+    S, _ = api.expand_entropy(torch.from_numpy(H).cuda(), 0.05, 0.1, m, 0.842704, prec=prec)
+    Srec, _ = R.entropy_expansion(H, 0.05, 0.1, m.theta, m.beta0, m.mu0, 0.842704)
+    rel = abs(float(S) - Srec) / Srec
+    print(f"[wide entropy {prec}] rel={rel:.3e}", flush=True)
+    assert rel <= (1e-11 if prec == "fp64" else 1e-5)
