@@ -158,6 +158,64 @@ int fe_batched_expand(const fe_batch_item* items, int32_t count, const fe_model*
                       const fe_model* mS, double alpha, int32_t prec, int32_t* status,
                       fe_workspace* ws, void* stream);
 
+/* ---- coefficient training (Sec. III.C) ------------------------------------------------- */
+#define FE_TARGET_FERMI    0   /* g(y) = 1/(1 + exp(beta0 (mu0 - y))) on the model coordinate */
+#define FE_TARGET_ENTROPY  1   /* -g ln g - (1-g) ln(1-g), model 4 ln2 u(1-u) with
+                                  u = layers(alpha (y - mu0) + mu0) (Eq. entropy expansion) */
+#define FE_SAMPLE_UNIFORM  0   /* sample density on [0, 1]: p ~ 1 */
+#define FE_SAMPLE_DERIV    1   /* p ~ 1 + |g'| */
+#define FE_SAMPLE_ARCLEN   2   /* p ~ sqrt(1 + g'^2) */
+
+typedef struct {
+    int32_t target;       /* FE_TARGET_* */
+    int32_t L;            /* layers, 1..96 */
+    double beta0, mu0;    /* training point (model coordinate) */
+    double alpha;         /* entropy input rescale (ignored for the Fermi target) */
+    int32_t n_points;     /* fixed sample points (quantiles of the sampling density), >= 4L */
+    int32_t sampling;     /* FE_SAMPLE_* */
+    int32_t max_iter;     /* Levenberg-Marquardt iterations */
+    double tol;           /* stop when max |model - target| over the points is below tol */
+} fe_train_spec;
+
+typedef struct {
+    int32_t iters;
+    double rms;             /* RMS residual over the sample points */
+    double max_err_points;  /* max |residual| over the sample points */
+    double max_err_grid;    /* max |model - target| on 200001 uniform points of [0, 1], FP64 */
+    double lambda;          /* final damping */
+} fe_train_report;
+
+/* Fit the coefficients by Levenberg-Marquardt with geodesic acceleration (Sec. III.C). Starts
+ * from theta_init (host L x 4) or, if NULL, from the SP2 embedding at mu0 (Eq. sp2-mu, App. C)
+ * over the layer count of Eq. (layer count) followed by identity layers. Residuals and the
+ * Jacobian run on the GPU in FP64; the damped normal equations are solved on the host.
+ * theta_out (host L x 4) receives the best coefficients. Synchronizes. Allocates its own device
+ * scratch for the duration of the call (the workspace argument is reserved, may be NULL).
+ * Returns FE_ERR_NO_CONVERGENCE (with theta_out filled) if tol was not reached. */
+int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double* theta_out,
+                    fe_train_report* rep, fe_workspace* ws, void* stream);
+
+/* The scalar model at n device points y (model coordinate), FP64: r = model(y) - tgt (tgt may be
+ * NULL), and if JT is not NULL the Jacobian transposed, JT[4i + c][k] = d model(y_k) /
+ * d theta_{i,c}. theta is host L x 4 (L <= 96). Asynchronous. */
+int fe_scalar_eval(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
+                   double mu0, double alpha, const double* tgt, double* r, double* JT, void* stream);
+
+/* FP32 matrix recursion for fitting on matrices: hist is device float32 (L+1) x n x n with
+ * hist[0] = X0 (symmetric, model coordinate) on entry; layer i writes X_{i+1} into hist[i+1]
+ * (FP32 MFMA); P (device n x n float32) receives A_L + X_L. n must be a multiple of 64. */
+int fe_matrix_forward(float* hist, int64_t n, const double* theta, int32_t L, float* P,
+                      void* stream);
+
+/* Backward of fe_matrix_forward: given G = dLoss/dP (device n x n float32, symmetric), writes
+ * grad (device float64 L x 4) = dLoss/dtheta: per layer one FP32 MFMA product
+ * M = Xb_{i+1} X_i and an elementwise pass Xb_i = a_i (M + M^T) + b_i Xb_{i+1} + d_i G with the
+ * coefficient gradients <M, X_i>, <Xb_{i+1}, X_i>, Tr Xb_{i+1}, <G, X_i> reduced in FP64.
+ * work: device float32 3 n^2; part: device float64 4 * nblocks (nblocks >= 1 reduction blocks). */
+int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_t L,
+                       const float* G, float* work, double* part, int32_t nblocks,
+                       double* grad, void* stream);
+
 /* ---- helpers ---------------------------------------------------------------------------- */
 
 /* SP2 for a known chemical potential embedded in the layer form (Eq. sp2-mu; App. C):

@@ -66,6 +66,10 @@ SIGNATURES = {
     "fe_expand_entropy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _D, _I32, _P,
                                  C.POINTER(fe_rescale_info), _P, _P]),
     "fe_sp2_coeffs": (_I32, [_D, _I32, C.POINTER(_D)]),
+    "fe_train_coeffs": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "fe_scalar_eval": (_I32, [_P, _I32, _P, _I32, _I32, _D, _D, _P, _P, _P, _P]),
+    "fe_matrix_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
+    "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
     "fe_last_error": (C.c_char_p, []),
     "fe_version": (C.c_char_p, []),

@@ -180,6 +180,38 @@ hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
                                const Params* P, int entropy, int32_t* status, hipStream_t s);
 
+// ---- coefficient training --------------------------------------------------------------
+constexpr int kScalarMaxL = 96;
+struct ScalarArgs {
+    const double* y;        // sample points (model coordinate), n
+    const double* tgt;      // target values or NULL (residual = model)
+    double* r;              // out: model - target, n
+    double* JT;             // out (or NULL): Jacobian transposed, 4L x n
+    int n, L, target;       // target 0: Fermi, 1: entropy
+    double mu0, alpha;
+    double theta[4 * kScalarMaxL];
+};
+int scalar_max_layers();
+hipError_t launch_scalar_eval(const ScalarArgs& a, hipStream_t s);
+hipError_t launch_gram(const double* JT, const double* v, int P, int n, double* G, double* g,
+                       hipStream_t s);
+struct MatTheta {
+    double v[4 * kScalarMaxL];
+};
+struct BwdArgs {
+    const float* M;         // Xb_{i+1} X_i
+    const float* Xb;        // Xb_{i+1}
+    const float* X;         // X_i
+    const float* G;         // dLoss/dP
+    float* Xb_out;          // Xb_i
+    float ca, cb, cd;       // a_i, b_i, d_i
+    int64_t n;
+    double* part;           // per-block partial sums, nblocks x 4
+};
+hipError_t launch_bwd_elem(const BwdArgs& a, int nblocks, double* grad4, hipStream_t s);
+hipError_t launch_fwd_out(const float* hist, int64_t n, int L, const MatTheta& th, float* P,
+                          hipStream_t s);
+
 // Deterministic reduction of tile partials: out_tr = sum tr, out_sq = sum sq; if entropy,
 // out_S = 4 ln2 (sum tr - sum sq).
 hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,

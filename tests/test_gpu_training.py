@@ -1,0 +1,102 @@
+"""GPU checks of the coefficient trainer: scalar residual/Jacobian kernel against the oracle's
+forward-mode Jacobian (which is pinned to finite differences), the LM fit's error level against
+the oracle's FP64 evaluation, and the FP32 matrix forward/backward autograd function against
+central finite differences of the FP64 oracle recursion.
+
+The fitted coefficients themselves are not unique (parity unpinned for theta); what is checked
+is the error level they reach, measured by the oracle."""
+import numpy as np
+import pytest
+
+from oracle import recursion as R
+from oracle import training as T
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_08523_amd import api, training
+    api.lib()
+    return training
+
+
+@pytest.mark.parametrize("kind", ["fermi", "entropy"])
+def test_scalar_jacobian_matches_oracle(tr, paper_model, kind):
+    th = paper_model.theta
+    y = T.sample_points(4096, 1500, 1 / 3, "deriv")
+    tgt = (T.fermi_target(y, 1500, 1 / 3) if kind == "fermi" else T.entropy_target(y, 1500, 1 / 3))
+    yd = torch.from_numpy(y).cuda()
+    r, JT = tr.scalar_eval(yd, th, kind, 1 / 3, 0.842704, tgt=torch.from_numpy(tgt).cuda())
+    torch.cuda.synchronize()
+    out, J = T.jacobian(y, th, kind, 1 / 3, 0.842704)
+    np.testing.assert_allclose(r.cpu().numpy(), out - tgt, rtol=0, atol=1e-12)
+    scale = np.max(np.abs(J), axis=0) + 1e-300
+    err = np.max(np.abs(JT.cpu().numpy().T - J) / scale)
+    print(f"[jacobian {kind}] max rel err {err:.3e}", flush=True)
+    assert err < 1e-10
+
+
+def test_train_small_model_reaches_error_level(tr):
+    """Sec. V.C: a 10-layer model trained at beta0 = 33.3, mu0 = 1/3, from the SP2 embedding."""
+    th, rep, ok = tr.train_coeffs(10, 33.3, 1 / 3, n_points=2048, max_iter=400, tol=1e-9)
+    err = T.max_model_error(th, 33.3, 1 / 3, n=200001)
+    print(f"[train L10 b33.3] iters={rep['iters']} device-report grid err={rep['max_err_grid']:.3e} "
+          f"oracle err={err:.3e}", flush=True)
+    assert err == pytest.approx(rep["max_err_grid"], rel=1e-6)
+    assert err < 3e-4
+
+
+def test_train_fig2_model(tr):
+    """Fig. 2 setting: 20 layers, beta = 308.3, mu = 1/2 (the paper shows MLSP2 near 1e-7)."""
+    th, rep, ok = tr.train_coeffs(20, 308.3, 0.5, n_points=4096, max_iter=1500, tol=1e-9)
+    err = T.max_model_error(th, 308.3, 0.5, n=200001)
+    print(f"[train L20 b308.3] iters={rep['iters']} oracle max err={err:.3e}", flush=True)
+    assert err < 5e-6
+
+
+def test_train_entropy_from_fermi_model(tr, paper_model):
+    """theta_entropy trained from theta_fermi (Sec. III.B), alpha = 0.842704."""
+    m = paper_model
+    e0 = T.max_model_error(m.theta, m.beta0, m.mu0, "entropy", 0.842704, n=200001)
+    th, rep, ok = tr.train_coeffs(m.L, m.beta0, m.mu0, target="entropy", alpha=0.842704,
+                                  n_points=8192, max_iter=300, tol=1e-10, theta_init=m.theta)
+    e1 = T.max_model_error(th, m.beta0, m.mu0, "entropy", 0.842704, n=200001)
+    print(f"[train entropy] start {e0:.3e} -> {e1:.3e} ({rep['iters']} iters)", flush=True)
+    assert e1 < e0 / 10
+
+
+def test_matrix_autograd_against_finite_differences(tr, paper_model):
+    rng = np.random.default_rng(5)
+    n, L = 64, 6
+    th = paper_model.theta[:L].copy()
+    Xs = rng.standard_normal((n, n))
+    X0 = (Xs + Xs.T) / (4 * np.sqrt(n)) + 0.4 * np.eye(n)
+    Tm = rng.standard_normal((n, n)) * 0.01
+    Tm = Tm + Tm.T
+
+    def loss64(t):
+        P = R.mlsp2_layers(X0, t)
+        return 0.5 * np.sum((P - Tm) ** 2)
+
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    P = tr.matrix_recursion(theta, torch.from_numpy(X0).float().cuda())
+    Pref = R.mlsp2_layers(X0, th)
+    assert np.max(np.abs(P.detach().double().cpu().numpy() - Pref)) < 1e-5
+    loss = 0.5 * torch.sum((P.double() - torch.from_numpy(Tm).cuda()) ** 2)
+    loss.backward()
+    g = theta.grad.numpy()
+    fd = np.zeros_like(th)
+    for i in range(L):
+        for c in range(4):
+            h = 1e-6
+            tp, tm = th.copy(), th.copy()
+            tp[i, c] += h
+            tm[i, c] -= h
+            fd[i, c] = (loss64(tp) - loss64(tm)) / (2 * h)
+    rel = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
+    print(f"[matrix autograd] max |g - fd| / max |fd| = {rel:.3e}", flush=True)
+    assert rel < 1e-3
