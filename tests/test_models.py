@@ -1,0 +1,15 @@
+"""The model bank: every stored coefficient table meets its recorded error, measured by the oracle."""
+import pytest
+
+from oracle import training as T
+from paper_2605_08523_amd import models
+
+
+@pytest.mark.parametrize("name", models.available())
+def test_model_bank_entry(name):
+    m = models.load(name)
+    assert m.theta.shape == (m.L, 4)
+    err = T.max_model_error(m.theta, m.beta0, m.mu0, n=200001)
+    recorded = m.meta.get("max_error", 5.960464477539063e-08)
+    assert err <= 1.01 * recorded
+    assert m.max_abs_layer() < 16.0          # inside the 16-bit operand range of the split modes
