@@ -39,7 +39,8 @@ int use_streamk(int64_t n, const fe_workspace* ws) {
     if (!ws->sk_partial) return 0;
     const char* env = getenv("FE_SCHEDULE");
     (void)n;
-    return env && env[0] == 's';
+    if (!env || env[0] != 's') return 0;
+    return strcmp(env, "sk2") == 0 ? 2 : 1;
 }
 
 int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
@@ -150,7 +151,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
     } else if (split) {
         fe::SplitPlan plan{};
         plan.streamk = use_streamk(n, ws);
-        plan.grid = ws->n_cu;
+        plan.grid = plan.streamk == 2 ? 2 * ws->n_cu : ws->n_cu;
         plan.partial = ws->sk_partial;
         plan.own = ws->sk_partial ? ws->sk_partial + (size_t)ws->n_cu * 256 * 256 : nullptr;
         plan.flags = ws->sk_flags;
@@ -250,8 +251,8 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ws->n_cu, hipDeviceAttributeMultiprocessorCount, ws->device);
     if (e == hipSuccess && max_n >= kStreamKMinN) {
         e = hipMalloc(reinterpret_cast<void**>(&ws->sk_partial), 2 * (size_t)ws->n_cu * 256 * 256 * sizeof(float));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_flags), (size_t)ws->n_cu * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMemset(ws->sk_flags, 0, (size_t)ws->n_cu * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_flags), 2 * (size_t)ws->n_cu * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(ws->sk_flags, 0, 2 * (size_t)ws->n_cu * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->sk_err), sizeof(int));
         if (e == hipSuccess) e = hipMemset(ws->sk_err, 0, sizeof(int));
     }

@@ -28,8 +28,9 @@ namespace {
 
 using namespace split;
 
-using CfgDP = Cfg<128, 2, 2, 32, 64, 1>;
-using CfgSK = Cfg<256, 2, 2, 32, 128, 2>;
+using CfgDP = Cfg<128, 2, 2, 64, 64, 1>;
+using CfgSK = Cfg<256, 2, 4, 32, 128, 2>;
+using CfgSK2 = Cfg<128, 2, 2, 64, 64, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
 
 constexpr int kSpinLimit = 1 << 22;   // ~0.2 s of s_sleep before a wait gives up
 
@@ -57,32 +58,72 @@ k_layer_dp(LayerArgs p) {
     epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, blockIdx.x);
 }
 
+// Thread 0 waits until the workgroups of group g with indices jlo .. j-1 have published their
+// partials of the current tile (each publishes exactly once: a group never has more workgroups
+// than iterations, so every range is non-empty). Their ids g + NG jlo, ..., w - NG are all smaller
+// than w. Bounded: a wait that gives up sets *err. Ends with a barrier.
+__device__ inline void wait_published(const SplitPlan& sk, int g, int NG, int jlo, int w) {
+    if (threadIdx.x == 0) {
+        bool gave_up = false;
+        for (int wp = g + NG * jlo; wp < w && !gave_up; wp += NG) {
+            int spins = 0;
+            while (__hip_atomic_load(sk.flags + wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                   sk.epoch) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(sk.err, 1);
+                    gave_up = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+    }
+    // The partials are read after this barrier, i.e. after the flags were seen, with
+    // device-coherent loads.
+    __syncthreads();
+}
+
 template <bool BF, class C>
-__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_layer_sk(LayerArgs p, SplitPlan sk) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    // Small tiles keep their accumulators in registers through the wait; large ones (256
+    // accumulator registers per lane) stage them to memory right after the K loop.
+    constexpr bool kRegEpi = C::MB * C::NB <= 4;
     const int tid = threadIdx.x;
-    const int w = blockIdx.x, G = sk.grid;
+    const int w = blockIdx.x;
     const int T = (int)(p.np / C::BM);
     const int ntiles = T * (T + 1) / 2;
     const int nk = (int)(p.np / C::BK);
-    const int64_t total = (int64_t)ntiles * nk;
-    const int64_t a_w = total * w / G, b_w = total * (w + 1) / G;
+    // The grid is split into NG groups (8 = one per XCD: the hardware hands workgroup w to XCD
+    // w % 8). Group g owns a contiguous block of tiles and runs stream-K over it with its GX
+    // workgroups, so a tile's contributors share one L2 and walk K roughly in step.
+    const int NG = sk.groups, g = w % NG, j = w / NG, GX = sk.grid / NG;
+    const int tg0 = (int)((int64_t)ntiles * g / NG), tg1 = (int)((int64_t)ntiles * (g + 1) / NG);
+    const int64_t base = (int64_t)tg0 * nk, total = (int64_t)(tg1 - tg0) * nk;
+    auto range_start = [&](int jj) { return base + total * jj / GX; };
+    const int64_t a_w = range_start(j), b_w = range_start(j + 1);
     constexpr size_t TILE = (size_t)C::BM * C::BM;
     float* own = sk.own + (size_t)w * TILE;
     float* pub = sk.partial + (size_t)w * TILE;
+    float* sY = reinterpret_cast<float*>(smem);
 
-    // Segments of [a_w, b_w): if the range stops inside its last tile, that tail segment is
-    // computed and published first, so that the workgroup finishing that tile never waits behind
-    // this workgroup's own waits (no chains of waits across the grid). Then the remaining
-    // segments, each of which finishes a tile, in order.
+    // Segments of [a_w, b_w), in three passes:
+    //  0: if the range stops inside its last tile, that tail segment, published first so that
+    //     the workgroup finishing that tile never waits behind this workgroup (no chains of
+    //     waits across the grid);
+    //  1: the segments that start on a tile boundary and finish their tile (no waiting);
+    //  2: if the range starts inside a tile, the rest of that tile, which waits for the earlier
+    //     workgroups' partials: last, so that they have had the longest time to publish.
     const int t_last = (int)((b_w - 1) / nk);
     const int64_t tail_start = (int64_t)t_last * nk > a_w ? (int64_t)t_last * nk : a_w;
     const bool publishes = b_w < (int64_t)(t_last + 1) * nk;
     const int64_t own_end = publishes ? tail_start : b_w;
-    for (int pass = publishes ? 0 : 1; pass < 2; ++pass) {
-        int64_t it = pass == 0 ? tail_start : a_w;
-        const int64_t stop = pass == 0 ? b_w : own_end;
+    const int64_t a_up = (a_w + nk - 1) / nk * nk;
+    const int64_t first_boundary = a_up < own_end ? a_up : own_end;
+    for (int pass = publishes ? 0 : 1; pass < 3; ++pass) {
+        int64_t it = pass == 0 ? tail_start : pass == 1 ? first_boundary : a_w;
+        const int64_t stop = pass == 0 ? b_w : pass == 1 ? own_end : first_boundary;
         while (it < stop) {
             const int t = (int)(it / nk);
             const int kb0 = (int)(it - (int64_t)t * nk);
@@ -90,50 +131,35 @@ k_layer_sk(LayerArgs p, SplitPlan sk) {
             const int kb1 = (int)((int64_t)kb0 + rest < nk ? kb0 + rest : nk);
             int I, J;
             tile_coords(t, T, I, J);
-            {
-                Acc<C> acc;
-                zero(acc);
-                kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, kb0,
-                             kb1, acc, reinterpret_cast<uint16_t*>(smem));
-                // The accumulators leave registers here: the published partial of the tile this
-                // workgroup stops inside, or its own share of a tile it finishes.
-                store_tile<BF, C>(acc, pass == 0 ? pub : own);
-            }
+            // Earlier workgroups of the group with indices jlo .. j-1 hold the first kb0 blocks
+            // of this tile; their partial slots are NG tiles apart. The epilogue adds them in a
+            // fixed order, so the result does not depend on timing.
+            int jlo = j;
+            if (pass != 0 && kb0 > 0)
+                while (jlo > 0 && range_start(jlo) > (int64_t)t * nk) --jlo;
+            const float* parts = sk.partial + (size_t)(g + NG * jlo) * TILE;
+            Acc<C> acc;
+            zero(acc);
+            kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, kb0, kb1,
+                         acc, reinterpret_cast<uint16_t*>(smem));
             if (pass == 0) {
-                __threadfence();
+                // Publication: every wave waits until its device-coherent stores of the partial
+                // have completed, then one flag store (device-coherent too) announces the tile.
+                // No release fence: on this chip it writes back the whole L2, and the readers'
+                // acquire would invalidate it; the partial needs neither (see store_coherent).
+                store_tile<BF, C, true>(acc, pub);
+                __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (tid == 0)
-                    __hip_atomic_store(sk.flags + w, sk.epoch, __ATOMIC_RELEASE,
+                    __hip_atomic_store(sk.flags + w, sk.epoch, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+            } else if constexpr (kRegEpi) {
+                wait_published(sk, g, NG, jlo, w);
+                epilogue<BF, C>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
             } else {
-                // Earlier workgroups wlo..w-1 hold the first kb0 blocks of this tile; their
-                // partial slots are contiguous. Wait for all of them; the epilogue adds them in a
-                // fixed order, so the result does not depend on timing.
-                int wlo = w;
-                if (kb0 > 0) {
-                    while (wlo > 0 && total * wlo / G > (int64_t)t * nk) --wlo;
-                    if (tid == 0) {
-                        // every workgroup wlo..w-1 has a non-empty range inside this tile (the
-                        // grid never exceeds the iteration count), so each publishes exactly once
-                        bool gave_up = false;
-                        for (int wp = wlo; wp < w && !gave_up; ++wp) {
-                            int spins = 0;
-                            while (__hip_atomic_load(sk.flags + wp, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT) != sk.epoch) {
-                                if (++spins > kSpinLimit) {
-                                    atomicOr(sk.err, 1);
-                                    gave_up = true;
-                                    break;
-                                }
-                                __builtin_amdgcn_s_sleep(2);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-                if (kb0 > 0) __threadfence();
-                epilogue_mem<BF, C>(p, own, sk.partial + (size_t)wlo * TILE, w - wlo,
-                                    reinterpret_cast<float*>(smem), I, J, t);
+                store_tile<BF, C, false>(acc, own);
+                wait_published(sk, g, NG, jlo, w);
+                epilogue_mem<BF, C>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
             }
             it += kb1 - kb0;
         }
@@ -161,19 +187,25 @@ hipError_t launch_dp(const LayerArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool BF>
+template <bool BF, class C>
 hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
-    using C = CfgSK;
     auto kern = k_layer_sk<BF, C>;
     static bool done = false;
     hipError_t e = set_lds(kern, C::LDS_BYTES, done);
     if (e != hipSuccess) return e;
-    // One workgroup per CU, but never more workgroups than (tile, K-block) iterations: then
-    // every workgroup's range is non-empty and each tile's earlier contributors all publish.
+    // One workgroup per CU, but never more workgroups per group than the group's (tile,
+    // K-block) iterations: then every range is non-empty and each tile's earlier contributors
+    // all publish. Eight groups (one per XCD) when every XCD gets at least one tile and enough
+    // iterations, else one group over the whole grid.
     const int64_t T = a.np / C::BM;
-    const int64_t total = T * (T + 1) / 2 * (a.np / C::BK);
+    const int64_t ntiles = T * (T + 1) / 2, nk = a.np / C::BK;
     SplitPlan plan = sk;
-    if (plan.grid > total) plan.grid = (int)total;
+    if (ntiles >= 8 && plan.grid % 8 == 0 && (ntiles / 8) * nk >= plan.grid / 8) {
+        plan.groups = 8;
+    } else {
+        plan.groups = 1;
+        if (plan.grid > ntiles * nk) plan.grid = (int)(ntiles * nk);
+    }
     if (plan.grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3(plan.grid), dim3(C::NT), C::LDS_BYTES, s, a, plan);
     return hipGetLastError();
@@ -181,10 +213,15 @@ hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
 
 }  // namespace
 
-int split_tile_for(int streamk) { return streamk ? CfgSK::BM : CfgDP::BM; }
+int split_tile_for(int streamk) {
+    return streamk == 1 ? CfgSK::BM : streamk == 2 ? CfgSK2::BM : CfgDP::BM;
+}
 
 hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s) {
-    if (plan.streamk) return bf16 ? launch_sk<true>(a, plan, s) : launch_sk<false>(a, plan, s);
+    if (plan.streamk == 1)
+        return bf16 ? launch_sk<true, CfgSK>(a, plan, s) : launch_sk<false, CfgSK>(a, plan, s);
+    if (plan.streamk == 2)
+        return bf16 ? launch_sk<true, CfgSK2>(a, plan, s) : launch_sk<false, CfgSK2>(a, plan, s);
     return bf16 ? launch_dp<true>(a, s) : launch_dp<false>(a, s);
 }
 

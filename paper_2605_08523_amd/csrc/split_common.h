@@ -13,6 +13,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 16-bit operands
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));   // 4 16-bit values
 
 // x = hi + lo / s with s = 2^11 for FP16 (keeps lo out of the FP16 subnormals) and s = 1 for BF16;
 // x - hi is exact in FP32, lo is its rounding.
@@ -91,7 +92,7 @@ struct Cfg {
     static constexpr int MB = WAVE_M / 32, NB = WAVE_N / 32;
     static constexpr int CPR = BK / 8;                // 16-byte chunks per panel row
     static constexpr int CH = BM * CPR / NT;          // chunks per thread per array
-    static constexpr int LDY = BM + 1;                // epilogue staging row (floats)
+    static constexpr int LDY = BM + 4;                // epilogue staging row (floats, 16-B aligned)
     static constexpr size_t STAGE_ELEMS = (size_t)4 * BM * LDK;
     static constexpr size_t KLOOP_BYTES = STAGES * STAGE_ELEMS * sizeof(uint16_t);
     static constexpr size_t EPI_BYTES = (size_t)EC * LDY * sizeof(float);
@@ -99,6 +100,7 @@ struct Cfg {
     static_assert(BM * CPR % NT == 0, "load split");
     static_assert(WAVE_M % 32 == 0 && WAVE_N % 32 == 0, "wave tile");
     static_assert(BM % EC == 0 && EC % 32 == 0 && (EC * BM) % NT == 0, "epilogue chunk");
+    static_assert(EC % 16 == 0 && LDY % 4 == 0, "vectorised epilogue");
 };
 
 template <class C>
@@ -217,19 +219,48 @@ __device__ inline void kloop(const uint16_t* __restrict__ hin, const uint16_t* _
     }
 }
 
-// Fused epilogue of tile (I, J), I <= J, from the accumulators (which hold s X^2):
-//   X' = a X^2 + b X + c delta_ij;  A += d_next X';  write the FP32 master, the next layer's
-//   hi/lo (tile and mirror).  On the last layer: D = A + X' (delta_ij - D if flipped), written to
-//   the tile and its mirror, or (entropy) U = A + X' traced only; FP64 partial traces per tile.
+// Four consecutive values split into hi/lo, each packed for one 8-byte store.
+template <bool BF>
+__device__ inline void split4(floatx4 v, u32x2& h, u32x2& l) {
+    uint16_t h0, l0, h1, l1, h2, l2, h3, l3;
+    split16<BF>(v[0], h0, l0);
+    split16<BF>(v[1], h1, l1);
+    split16<BF>(v[2], h2, l2);
+    split16<BF>(v[3], h3, l3);
+    h = u32x2{(unsigned)h0 | ((unsigned)h1 << 16), (unsigned)h2 | ((unsigned)h3 << 16)};
+    l = u32x2{(unsigned)l0 | ((unsigned)l1 << 16), (unsigned)l2 | ((unsigned)l3 << 16)};
+}
+
+// Device-coherent (agent scope) 32-bit accesses. Each one is coherent across the XCDs' L2
+// caches by itself (global_store/load with sc1), so data handed between workgroups this way needs
+// no cache-wide write-back or invalidate: those would also throw away the operand panels that
+// every other workgroup of the XCD is streaming through the same L2.
+__device__ inline void store_coherent(float* p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float load_coherent(const float* p) {
+    return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One chunk (tile rows R0 .. R0+EC-1) of the fused epilogue of tile (I, J), I <= J:
+//   Y = X^2 (from sY, or from the row-major BM x BM tile Y0 in memory if Y0 is set) plus the
+//   partial tiles parts[0..nparts-1] (part_stride floats apart, written by other workgroups and
+//   read device-coherently, added in this order);
+//   X' = a Y + b X + c delta_ij;  A += d_next X';  write the FP32 master and the next layer's
+//   hi/lo for the tile (row-major pass, four columns per thread) and its mirror (transposed pass
+//   through sY, four rows per thread). On the last layer: D = A + X' (delta_ij - D if flipped)
+//   written to the tile and its mirror, or (entropy) U = A + X' traced only; FP64 trace sums
+//   accumulate in tr, sq. Diagonal tiles keep only the upper triangle of X and A, and their lower
+//   half of hi/lo (or D) comes from the mirror pass, so every stored matrix is exactly symmetric.
+// Ends with a barrier (sY is free again).
 template <bool BF, class C>
-__device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY, int I, int J,
-                                int tile_index) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / C::WN, wn = wave % C::WN;
+__device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, int J,
+                                 const float* __restrict__ Y0, const float* __restrict__ parts,
+                                 size_t part_stride, int nparts, double& tr, double& sq) {
+    const int tid = threadIdx.x;
     const int64_t np = p.np;
     const int64_t I0 = (int64_t)I * C::BM, J0 = (int64_t)J * C::BM;
     const bool diag = (I == J);
-    const float inv_s = BF ? 1.0f : (1.0f / 2048.0f);
     const float ca = p.a, cb = p.b, cc = p.c, dn = p.d_next;
     const bool last = p.last != 0;
     const bool ent = p.entropy != 0;
@@ -237,8 +268,164 @@ __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY
     const int64_t n = p.n;
     float* __restrict__ X = p.X;
     float* __restrict__ A = p.A;
-    double tr = 0.0, sq = 0.0;
+    constexpr int G = C::BM / 4;   // four-column groups per tile row
 
+#pragma unroll 2
+    for (int e = tid; e < C::EC * G; e += C::NT) {
+        const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
+        if (diag && c + 3 < r) continue;   // entirely below the diagonal
+        const int loc = r * C::BM + c;
+        float* srow = sY + rl * C::LDY + c;
+        floatx4 y = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
+                       : *reinterpret_cast<const floatx4*>(srow);
+        for (int q = 0; q < nparts; ++q) {
+            const float* pp = parts + (size_t)q * part_stride + loc;
+            y[0] += load_coherent(pp);
+            y[1] += load_coherent(pp + 1);
+            y[2] += load_coherent(pp + 2);
+            y[3] += load_coherent(pp + 3);
+        }
+        const int64_t gr = I0 + r, gc = J0 + c;
+        const int64_t gi = gr * np + gc;
+        const floatx4 x = *reinterpret_cast<const floatx4*>(X + gi);
+        floatx4 xn;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xn[k] = fmaf(ca, y[k], fmaf(cb, x[k], gr == gc + k ? cc : 0.0f));
+        const bool full = !diag || c >= r;
+        if (!last) {
+            if (full) {
+                *reinterpret_cast<floatx4*>(X + gi) = xn;
+                if (dn != 0.0f) {
+                    floatx4 a4 = *reinterpret_cast<const floatx4*>(A + gi);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) a4[k] = fmaf(dn, xn[k], a4[k]);
+                    *reinterpret_cast<floatx4*>(A + gi) = a4;
+                }
+                u32x2 h, l;
+                split4<BF>(xn, h, l);
+                *reinterpret_cast<u32x2*>(p.hi_out + gi) = h;
+                *reinterpret_cast<u32x2*>(p.lo_out + gi) = l;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c + k < r) continue;
+                    X[gi + k] = xn[k];
+                    if (dn != 0.0f) A[gi + k] = fmaf(dn, xn[k], A[gi + k]);
+                    uint16_t h, l;
+                    split16<BF>(xn[k], h, l);
+                    p.hi_out[gi + k] = h;
+                    p.lo_out[gi + k] = l;
+                }
+            }
+            *reinterpret_cast<floatx4*>(srow) = xn;
+        } else {
+            floatx4 out;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t gck = gc + k;
+                double v = (double)A[gi + k] + (double)xn[k];
+                if (flip) v = (gr == gck ? 1.0 : 0.0) - v;
+                const float vf = ent ? 0.0f : (float)v;
+                const double vo = ent ? v : (double)vf;
+                if ((!diag || c + k >= r) && gr < n && gck < n) {
+                    if (gr == gck) tr += vo;
+                    sq += (gr == gck ? 1.0 : 2.0) * vo * vo;
+                    if (!ent) {
+                        if (p.out_mode == 0)
+                            reinterpret_cast<float*>(p.D)[gr * p.ldd + gck] = vf;
+                        else if (p.out_mode == 1)
+                            reinterpret_cast<double*>(p.D)[gr * p.ldd + gck] = (double)vf;
+                    }
+                }
+                out[k] = vf;
+            }
+            *reinterpret_cast<floatx4*>(srow) = out;
+        }
+    }
+    __syncthreads();
+    if (!last) {
+        // Mirror: output row J0 + c, four consecutive output columns I0 + r .. r+3 per thread;
+        // four neighbouring threads cover 16 contiguous columns of one output row.
+        constexpr int RG = C::EC / 4;
+#pragma unroll 2
+        for (int e = tid; e < C::BM * RG; e += C::NT) {
+            const int c = (e >> 2) % C::BM;
+            const int rl = ((((e >> 2) / C::BM) << 2) + (e & 3)) * 4, r = R0 + rl;
+            if (diag && r >= c) continue;   // nothing strictly below the diagonal
+            floatx4 v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = sY[(rl + k) * C::LDY + c];
+            const int64_t oi = (J0 + c) * np + I0 + r;
+            if (!diag || r + 3 < c) {
+                u32x2 h, l;
+                split4<BF>(v, h, l);
+                *reinterpret_cast<u32x2*>(p.hi_out + oi) = h;
+                *reinterpret_cast<u32x2*>(p.lo_out + oi) = l;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (r + k >= c) continue;
+                    uint16_t h, l;
+                    split16<BF>(v[k], h, l);
+                    p.hi_out[oi + k] = h;
+                    p.lo_out[oi + k] = l;
+                }
+            }
+        }
+    } else if (!(ent || p.out_mode == 2)) {
+#pragma unroll 4
+        for (int e = tid; e < C::EC * C::BM; e += C::NT) {
+            const int rl = e % C::EC, c = e / C::EC, r = R0 + rl;
+            if (diag && !(r < c)) continue;
+            const float v = sY[rl * C::LDY + c];
+            const int64_t orow = J0 + c, ocol = I0 + r;
+            if (orow < n && ocol < n) {
+                if (p.out_mode == 0)
+                    reinterpret_cast<float*>(p.D)[orow * p.ldd + ocol] = v;
+                else
+                    reinterpret_cast<double*>(p.D)[orow * p.ldd + ocol] = (double)v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Per-tile FP64 trace partials of the last layer, reduced over the workgroup in a fixed order.
+template <class C>
+__device__ inline void write_traces(const LayerArgs& p, double tr, double sq, float* sY,
+                                    int tile_index) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    tr = wave_sum(tr);
+    sq = wave_sum(sq);
+    double* red = reinterpret_cast<double*>(sY);
+    if (lane == 0) {
+        red[2 * wave] = tr;
+        red[2 * wave + 1] = sq;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0, s = 0.0;
+        for (int w = 0; w < C::NT / 64; ++w) {
+            t += red[2 * w];
+            s += red[2 * w + 1];
+        }
+        p.partials[tile_index].tr = t;
+        p.partials[tile_index].sq = s;
+    }
+    __syncthreads();
+}
+
+// Fused epilogue of tile (I, J), I <= J, from the accumulators (which hold s X^2), plus optional
+// partial tiles of other workgroups (see epi_chunk). The accumulators go through sY EC rows at a
+// time.
+template <bool BF, class C>
+__device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY, int I, int J,
+                                int tile_index, const float* __restrict__ parts = nullptr,
+                                size_t part_stride = 0, int nparts = 0) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const float inv_s = BF ? 1.0f : (1.0f / 2048.0f);
+    double tr = 0.0, sq = 0.0;
 #pragma unroll 1
     for (int ch = 0; ch < C::BM / C::EC; ++ch) {
         const int R0 = ch * C::EC;
@@ -259,90 +446,15 @@ __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY
             }
         }
         __syncthreads();
-#pragma unroll 4
-        for (int e = tid; e < C::EC * C::BM; e += C::NT) {
-            const int rl = e / C::BM, c = e % C::BM, r = R0 + rl;
-            if (diag && r > c) continue;
-            const int64_t gr = I0 + r, gc = J0 + c;
-            const int64_t gi = gr * np + gc;
-            const float y = sY[rl * C::LDY + c];
-            const float x = X[gi];
-            const float xn = fmaf(ca, y, fmaf(cb, x, gr == gc ? cc : 0.0f));
-            if (!last) {
-                X[gi] = xn;
-                if (dn != 0.0f) A[gi] = fmaf(dn, xn, A[gi]);
-                uint16_t h, l;
-                split16<BF>(xn, h, l);
-                p.hi_out[gi] = h;
-                p.lo_out[gi] = l;
-                sY[rl * C::LDY + c] = xn;
-            } else {
-                double v = (double)A[gi] + (double)xn;
-                if (flip) v = (gr == gc ? 1.0 : 0.0) - v;
-                const float vf = ent ? 0.0f : (float)v;
-                const double vo = ent ? v : (double)vf;
-                if (gr < n && gc < n) {
-                    if (gr == gc) tr += vo;
-                    sq += (gr == gc ? 1.0 : 2.0) * vo * vo;
-                    if (!ent) {
-                        if (p.out_mode == 0)
-                            reinterpret_cast<float*>(p.D)[gr * p.ldd + gc] = vf;
-                        else if (p.out_mode == 1)
-                            reinterpret_cast<double*>(p.D)[gr * p.ldd + gc] = (double)vf;
-                    }
-                }
-                sY[rl * C::LDY + c] = vf;
-            }
-        }
-        __syncthreads();
-        if (!(last && (ent || p.out_mode == 2))) {
-#pragma unroll 4
-            for (int e = tid; e < C::EC * C::BM; e += C::NT) {
-                const int rl = e % C::EC, c = e / C::EC, r = R0 + rl;
-                if (diag && !(r < c)) continue;
-                const float v = sY[rl * C::LDY + c];
-                const int64_t orow = J0 + c, ocol = I0 + r;
-                if (!last) {
-                    uint16_t h, l;
-                    split16<BF>(v, h, l);
-                    p.hi_out[orow * np + ocol] = h;
-                    p.lo_out[orow * np + ocol] = l;
-                } else if (orow < n && ocol < n) {
-                    if (p.out_mode == 0)
-                        reinterpret_cast<float*>(p.D)[orow * p.ldd + ocol] = v;
-                    else
-                        reinterpret_cast<double*>(p.D)[orow * p.ldd + ocol] = (double)v;
-                }
-            }
-        }
-        __syncthreads();
+        epi_chunk<BF, C>(p, sY, R0, I, J, nullptr, parts, part_stride, nparts, tr, sq);
     }
-
-    if (last) {
-        tr = wave_sum(tr);
-        sq = wave_sum(sq);
-        double* red = reinterpret_cast<double*>(sY);
-        if (lane == 0) {
-            red[2 * wave] = tr;
-            red[2 * wave + 1] = sq;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0, s = 0.0;
-            for (int w = 0; w < C::NT / 64; ++w) {
-                t += red[2 * w];
-                s += red[2 * w + 1];
-            }
-            p.partials[tile_index].tr = t;
-            p.partials[tile_index].sq = s;
-        }
-        __syncthreads();
-    }
+    if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
 
-// Store the accumulators of a BM x BM tile (scaled by 1/s, i.e. as X^2) row-major into dst.
+// Store the accumulators of a BM x BM tile (scaled by 1/s, i.e. as X^2) row-major into dst,
+// with device-coherent stores if COHERENT (a tile another workgroup reads), else plain ones.
 // Each store instruction writes two 128-byte row segments.
-template <bool BF, class C>
+template <bool BF, class C, bool COHERENT>
 __device__ inline void store_tile(const Acc<C>& acc, float* __restrict__ dst) {
     int tid = threadIdx.x;
     // Opaque to the optimiser: inside a persistent loop the 256 element offsets below would
@@ -360,115 +472,25 @@ __device__ inline void store_tile(const Acc<C>& acc, float* __restrict__ dst) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int r = rb + 8 * (j >> 2) + (j & 3);
-                dst[r * C::BM + cl] = acc.v[mb][nb][j] * inv_s;
+                if constexpr (COHERENT)
+                    store_coherent(dst + r * C::BM + cl, acc.v[mb][nb][j] * inv_s);
+                else
+                    dst[r * C::BM + cl] = acc.v[mb][nb][j] * inv_s;
             }
         }
 }
 
 // Fused epilogue of tile (I, J), I <= J, reading X^2 from memory: Y = Y0 + parts[0] + ... +
-// parts[nparts-1] (row-major BM x BM FP32 tiles, added in this order). Same outputs as
-// `epilogue`; X' is staged through LDS (EC rows at a time) for the transposed mirror pass.
+// parts[nparts-1] (Y0 row-major BM x BM, written by this workgroup; see epi_chunk).
 template <bool BF, class C>
 __device__ inline void epilogue_mem(const LayerArgs& p, const float* __restrict__ Y0,
-                                    const float* __restrict__ parts, int nparts, float* sY, int I,
-                                    int J, int tile_index) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t np = p.np;
-    const int64_t I0 = (int64_t)I * C::BM, J0 = (int64_t)J * C::BM;
-    const bool diag = (I == J);
-    const float ca = p.a, cb = p.b, cc = p.c, dn = p.d_next;
-    const bool last = p.last != 0;
-    const bool ent = p.entropy != 0;
-    const int flip = (last && !ent) ? p.P->flipped : 0;
-    const int64_t n = p.n;
-    float* __restrict__ X = p.X;
-    float* __restrict__ A = p.A;
+                                    const float* __restrict__ parts, size_t part_stride,
+                                    int nparts, float* sY, int I, int J, int tile_index) {
     double tr = 0.0, sq = 0.0;
-
 #pragma unroll 1
-    for (int ch = 0; ch < C::BM / C::EC; ++ch) {
-        const int R0 = ch * C::EC;
-#pragma unroll 4
-        for (int e = tid; e < C::EC * C::BM; e += C::NT) {
-            const int rl = e / C::BM, c = e % C::BM, r = R0 + rl;
-            if (diag && r > c) continue;
-            const int loc = r * C::BM + c;
-            float y = Y0[loc];
-            for (int q = 0; q < nparts; ++q) y += parts[(size_t)q * C::BM * C::BM + loc];
-            const int64_t gr = I0 + r, gc = J0 + c;
-            const int64_t gi = gr * np + gc;
-            const float x = X[gi];
-            const float xn = fmaf(ca, y, fmaf(cb, x, gr == gc ? cc : 0.0f));
-            if (!last) {
-                X[gi] = xn;
-                if (dn != 0.0f) A[gi] = fmaf(dn, xn, A[gi]);
-                uint16_t h, l;
-                split16<BF>(xn, h, l);
-                p.hi_out[gi] = h;
-                p.lo_out[gi] = l;
-                sY[rl * C::LDY + c] = xn;
-            } else {
-                double v = (double)A[gi] + (double)xn;
-                if (flip) v = (gr == gc ? 1.0 : 0.0) - v;
-                const float vf = ent ? 0.0f : (float)v;
-                const double vo = ent ? v : (double)vf;
-                if (gr < n && gc < n) {
-                    if (gr == gc) tr += vo;
-                    sq += (gr == gc ? 1.0 : 2.0) * vo * vo;
-                    if (!ent) {
-                        if (p.out_mode == 0)
-                            reinterpret_cast<float*>(p.D)[gr * p.ldd + gc] = vf;
-                        else if (p.out_mode == 1)
-                            reinterpret_cast<double*>(p.D)[gr * p.ldd + gc] = (double)vf;
-                    }
-                }
-                sY[rl * C::LDY + c] = vf;
-            }
-        }
-        __syncthreads();
-        if (!(last && (ent || p.out_mode == 2))) {
-#pragma unroll 4
-            for (int e = tid; e < C::EC * C::BM; e += C::NT) {
-                const int rl = e % C::EC, c = e / C::EC, r = R0 + rl;
-                if (diag && !(r < c)) continue;
-                const float v = sY[rl * C::LDY + c];
-                const int64_t orow = J0 + c, ocol = I0 + r;
-                if (!last) {
-                    uint16_t h, l;
-                    split16<BF>(v, h, l);
-                    p.hi_out[orow * np + ocol] = h;
-                    p.lo_out[orow * np + ocol] = l;
-                } else if (orow < n && ocol < n) {
-                    if (p.out_mode == 0)
-                        reinterpret_cast<float*>(p.D)[orow * p.ldd + ocol] = v;
-                    else
-                        reinterpret_cast<double*>(p.D)[orow * p.ldd + ocol] = (double)v;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    if (last) {
-        tr = wave_sum(tr);
-        sq = wave_sum(sq);
-        double* red = reinterpret_cast<double*>(sY);
-        if (lane == 0) {
-            red[2 * wave] = tr;
-            red[2 * wave + 1] = sq;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0, s = 0.0;
-            for (int w = 0; w < C::NT / 64; ++w) {
-                t += red[2 * w];
-                s += red[2 * w + 1];
-            }
-            p.partials[tile_index].tr = t;
-            p.partials[tile_index].sq = s;
-        }
-        __syncthreads();
-    }
+    for (int ch = 0; ch < C::BM / C::EC; ++ch)
+        epi_chunk<BF, C>(p, sY, ch * C::EC, I, J, Y0, parts, part_stride, nparts, tr, sq);
+    if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
 
 }  // namespace split

@@ -202,18 +202,27 @@ def test_entropy_against_oracle(api, paper_model, prec):
     assert abs(S - Srec) <= tol * abs(Srec)
 
 
-@pytest.mark.parametrize("schedule", ["dp", "sk"])
+@pytest.fixture(scope="module")
+def sk_ws(api):
+    """A workspace large enough to carry the stream-K buffers, so that small n use them too."""
+    ws = api.Workspace(2048)
+    yield ws
+    torch.cuda.synchronize()
+    ws.close()
+
+
+@pytest.mark.parametrize("schedule", ["dp", "sk", "sk2"])
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
 @pytest.mark.parametrize("name,n,seed", [("dense300", 300, 21), ("dense1000", 1000, 22),
                                          ("banded1700", 1700, 23)])
-def test_both_schedules(api, paper_model, monkeypatch, schedule, prec, name, n, seed):
+def test_both_schedules(api, sk_ws, paper_model, monkeypatch, schedule, prec, name, n, seed):
     """Data-parallel and stream-K schedules on ragged sizes (many-way split tiles for small n)."""
     monkeypatch.setenv("FE_SCHEDULE", schedule)
     m = paper_model
     H = W.random_dense(n, seed) if name.startswith("dense") else W.banded_decay(n, 8.0, 2.0, seed)
     mu, kT = 0.1, 0.1
     print(f"case {name} {prec} schedule={schedule}", flush=True)
-    D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec)
+    D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec, ws=sk_ws)
     Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
     fro, _ = report(f"{name} {prec} {schedule} vs recursion", D, Drec)
     assert torch.equal(Dt, Dt.T)
@@ -221,16 +230,18 @@ def test_both_schedules(api, paper_model, monkeypatch, schedule, prec, name, n, 
     assert tr == pytest.approx(np.trace(D), abs=1e-9 * n)
 
 
-def test_schedules_agree(api, paper_model, monkeypatch):
-    """The two schedules sum the same products in different tile shapes: results agree closely."""
+def test_schedules_agree(api, sk_ws, paper_model, monkeypatch):
+    """The schedules sum the same products in different tile shapes: results agree closely."""
     m = paper_model
     H = W.random_dense(1100, 24)
     out = {}
-    for sch in ("dp", "sk"):
+    for sch in ("dp", "sk", "sk2"):
         monkeypatch.setenv("FE_SCHEDULE", sch)
-        out[sch] = run(api, H, 0.05, 0.1, m, "fp16x2")[0]
+        out[sch] = run(api, H, 0.05, 0.1, m, "fp16x2", ws=sk_ws)[0]
     assert np.max(np.abs(out["dp"] - out["sk"])) < 1e-4
+    assert np.max(np.abs(out["dp"] - out["sk2"])) < 1e-4
     # stream-K is deterministic: a second run is bitwise identical
-    monkeypatch.setenv("FE_SCHEDULE", "sk")
-    again = run(api, H, 0.05, 0.1, m, "fp16x2")[0]
-    assert np.array_equal(again, out["sk"])
+    for sch in ("sk", "sk2"):
+        monkeypatch.setenv("FE_SCHEDULE", sch)
+        again = run(api, H, 0.05, 0.1, m, "fp16x2", ws=sk_ws)[0]
+        assert np.array_equal(again, out[sch])
