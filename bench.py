@@ -37,6 +37,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only a plain 1 GiB device-to-device copy, three times (the reference for "
+                        "scaling the HBM byte counters)")
     return p.parse_args()
 
 
@@ -55,6 +58,28 @@ def timed(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps     # ms per call
 
 
+KERNEL_SOURCES = ("fe_api.hip", "fe_internal.h", "k_layer_split.hip", "split_common.h")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_counters_anderson4096.md")
+
+
+def measured_traffic():
+    """HBM bytes per layer launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
+    (copy-calibrated), or None if the layer kernel's sources changed since it was taken."""
+    import hashlib
+    try:
+        line = next(l for l in open(COUNTER_SUMMARY) if l.startswith("traffic_json:"))
+        rec = json.loads(line.split(":", 1)[1])
+    except (OSError, StopIteration, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_08523_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -68,6 +93,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        x = torch.ones(256 * 2**20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copy calibration done: 3 copies of 1 GiB", flush=True)
+        return
     m = models.load("mlsp2_L26_b1500_mu1third")
     c = workloads.config_anderson_4096()
     H = c["H"]
@@ -131,7 +164,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "layer_ms": layer_ms,
             "executed_mfma_tflops": exec_flop_layer / (layer_ms * 1e-3) / 1e12,
             "executed_frac": exec_flop_layer / (layer_ms * 1e-3) / 1e12 / peak,

@@ -32,15 +32,24 @@ int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, 
 
 constexpr int64_t kStreamKMinN = 1536;   // workspaces for n >= this carry stream-K buffers
 
-// Schedule of the split-precision layer kernel: data-parallel by default (measured faster at
-// N = 4096 so far); FE_SCHEDULE=sk selects the persistent stream-K schedule, FE_SCHEDULE=dp the
-// data-parallel one.
+// Schedule of the split-precision layer kernel (FE_SCHEDULE=dp|sk|sk2 overrides):
+//  0 data-parallel, 128 x 128 tiles, one workgroup per upper tile;
+//  1 stream-K over 256 x 256 tiles, one workgroup per CU;
+//  2 stream-K over 128 x 128 tiles, two workgroups per CU (whole-tile rounds first when there
+//    are two or more rounds).
+// Default: 2 when every stream-K workgroup gets at least eight K-blocks (else the partial-tile
+// traffic outweighs the balance: measured slower below N ~ 2000), otherwise 0. Only workspaces
+// sized for n >= kStreamKMinN carry the stream-K buffers.
 int use_streamk(int64_t n, const fe_workspace* ws) {
     if (!ws->sk_partial) return 0;
     const char* env = getenv("FE_SCHEDULE");
-    (void)n;
-    if (!env || env[0] != 's') return 0;
-    return strcmp(env, "sk2") == 0 ? 2 : 1;
+    if (env && env[0] == 'd') return 0;
+    if (env && env[0] == 's') return strcmp(env, "sk2") == 0 ? 2 : 1;
+    const int64_t np = round_up(n, 128), T = np / 128, ntiles = T * (T + 1) / 2, nk = np / 64;
+    const int64_t grid = 2 * (int64_t)ws->n_cu;
+    const int64_t rounds = ntiles / grid;
+    const int64_t nsk = rounds >= 2 ? ntiles - (rounds - 1) * grid : ntiles;
+    return nsk * nk >= 8 * grid ? 2 : 0;
 }
 
 int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {

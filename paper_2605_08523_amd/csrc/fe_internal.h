@@ -93,6 +93,7 @@ struct SplitPlan {
     int streamk;          // 0: one workgroup per 128 x 128 upper tile; 1: persistent stream-K
     int grid;             // stream-K workgroups (one per CU)
     int groups;           // stream-K groups (8: one per XCD), set by the launcher
+    int dp_tiles;         // leading tiles computed whole (data-parallel rounds), set by the launcher
     float* partial;       // stream-K published partial tiles, grid x 256 x 256 floats
     float* own;           // stream-K per-workgroup staging of finished tiles, grid x 256 x 256 floats
     uint32_t* flags;      // stream-K publication flags, one per workgroup (zero-initialised)

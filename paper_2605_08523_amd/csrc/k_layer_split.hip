@@ -11,16 +11,18 @@
 //  * The epilogue is fused (see split_common.h): Y goes through LDS, one row-major pass applies
 //    a Y + b X + c delta_ij, updates A with the next layer's d and writes the master and the next
 //    hi/lo; a transposed pass writes the mirror tile. The last layer writes D and FP64 traces.
-//  * Two schedules:
-//      data-parallel: one workgroup per upper tile (128 x 128, four 64 x 64 wave tiles), used when
-//        the matrix is small;
-//      stream-K: one persistent workgroup per CU (256 x 256 tiles, four 128 x 128 wave tiles,
-//        double-buffered LDS); the (tile, K-block) iterations are split evenly. Every segment
-//        stores its FP32 partial tile to memory (so the 256 accumulator registers die right after
-//        the K loop): a workgroup that stops inside a tile publishes it, the workgroup that
-//        finishes the tile runs the epilogue from memory, adding the earlier workgroups' partials
-//        in a fixed order. A workgroup only ever waits for workgroups with smaller ids, which were
-//        dispatched earlier, and every wait is bounded.
+//  * Three schedules:
+//      data-parallel: one workgroup per upper tile (128 x 128, four 64 x 64 wave tiles);
+//      stream-K over 128 x 128 tiles, two persistent workgroups per CU: the (tile, K-block)
+//        iterations left after the whole-tile rounds are split evenly. A workgroup that stops
+//        inside a tile publishes its FP32 partial; the workgroup that finishes the tile adds the
+//        earlier workgroups' partials in a fixed order in its epilogue (accumulators stay in
+//        registers);
+//      stream-K over 256 x 256 tiles (eight 128 x 64 wave tiles, double-buffered LDS), one
+//        workgroup per CU: the same, with every segment's accumulators staged through memory
+//        right after its K loop (128 per lane would not survive the epilogue in registers).
+//    A workgroup only ever waits for workgroups with smaller ids, which were dispatched earlier,
+//    and every wait is bounded.
 #include "split_common.h"
 
 namespace fe {
@@ -87,7 +89,7 @@ template <bool BF, class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_layer_sk(LayerArgs p, SplitPlan sk) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    // Small tiles keep their accumulators in registers through the wait; large ones (256
+    // Small tiles keep their accumulators in registers through the wait; large ones (128
     // accumulator registers per lane) stage them to memory right after the K loop.
     constexpr bool kRegEpi = C::MB * C::NB <= 4;
     const int tid = threadIdx.x;
@@ -95,18 +97,21 @@ k_layer_sk(LayerArgs p, SplitPlan sk) {
     const int T = (int)(p.np / C::BM);
     const int ntiles = T * (T + 1) / 2;
     const int nk = (int)(p.np / C::BK);
-    // The grid is split into NG groups (8 = one per XCD: the hardware hands workgroup w to XCD
-    // w % 8). Group g owns a contiguous block of tiles and runs stream-K over it with its GX
-    // workgroups, so a tile's contributors share one L2 and walk K roughly in step.
-    const int NG = sk.groups, g = w % NG, j = w / NG, GX = sk.grid / NG;
-    const int tg0 = (int)((int64_t)ntiles * g / NG), tg1 = (int)((int64_t)ntiles * (g + 1) / NG);
-    const int64_t base = (int64_t)tg0 * nk, total = (int64_t)(tg1 - tg0) * nk;
-    auto range_start = [&](int jj) { return base + total * jj / GX; };
-    const int64_t a_w = range_start(j), b_w = range_start(j + 1);
     constexpr size_t TILE = (size_t)C::BM * C::BM;
     float* own = sk.own + (size_t)w * TILE;
     float* pub = sk.partial + (size_t)w * TILE;
     float* sY = reinterpret_cast<float*>(smem);
+
+    // Tiles [0, dp_tiles) were computed whole by a data-parallel launch before this one.
+    // The stream-K grid is split into NG groups (8 = one per XCD: the hardware hands workgroup
+    // w to XCD w % 8). Group g owns a contiguous block of the remaining tiles and runs stream-K
+    // over it with its GX workgroups, so a tile's contributors share one L2.
+    const int t0 = sk.dp_tiles, nsk = ntiles - sk.dp_tiles;
+    const int NG = sk.groups, g = w % NG, j = w / NG, GX = sk.grid / NG;
+    const int tg0 = t0 + (int)((int64_t)nsk * g / NG), tg1 = t0 + (int)((int64_t)nsk * (g + 1) / NG);
+    const int64_t base = (int64_t)tg0 * nk, total = (int64_t)(tg1 - tg0) * nk;
+    auto range_start = [&](int jj) { return base + total * jj / GX; };
+    const int64_t a_w = range_start(j), b_w = range_start(j + 1);
 
     // Segments of [a_w, b_w), in three passes:
     //  0: if the range stops inside its last tile, that tail segment, published first so that
@@ -155,11 +160,11 @@ k_layer_sk(LayerArgs p, SplitPlan sk) {
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else if constexpr (kRegEpi) {
                 wait_published(sk, g, NG, jlo, w);
-                epilogue<BF, C>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
+                epilogue<BF, C, 2>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
             } else {
                 store_tile<BF, C, false>(acc, own);
                 wait_published(sk, g, NG, jlo, w);
-                epilogue_mem<BF, C>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
+                epilogue_mem<BF, C, 2>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
             }
             it += kb1 - kb0;
         }
@@ -200,13 +205,32 @@ hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
     const int64_t T = a.np / C::BM;
     const int64_t ntiles = T * (T + 1) / 2, nk = a.np / C::BK;
     SplitPlan plan = sk;
-    if (ntiles >= 8 && plan.grid % 8 == 0 && (ntiles / 8) * nk >= plan.grid / 8) {
+    // With two or more full rounds of tiles, all but the last round run as whole tiles in a
+    // data-parallel launch first (their K walks stay in step, which the L2 rewards), and
+    // stream-K balances the last round plus the remainder. Configurations that stage their
+    // accumulators through memory run stream-K alone.
+    const int64_t rounds = ntiles / plan.grid;
+    constexpr bool reg_epi = C::MB * C::NB <= 4;
+    plan.dp_tiles = (reg_epi && rounds >= 2) ? (int)((rounds - 1) * plan.grid) : 0;
+    const int64_t nsk = ntiles - plan.dp_tiles;
+    if (nsk >= 8 && plan.grid % 8 == 0 && (nsk / 8) * nk >= plan.grid / 8) {
         plan.groups = 8;
     } else {
         plan.groups = 1;
-        if (plan.grid > ntiles * nk) plan.grid = (int)(ntiles * nk);
+        if (plan.grid > nsk * nk) plan.grid = (int)(nsk * nk);
     }
     if (plan.grid < 1) return hipErrorInvalidValue;
+    if constexpr (reg_epi) {
+        if (plan.dp_tiles > 0) {
+            auto dkern = k_layer_dp<BF, C>;
+            static bool ddone = false;
+            e = set_lds(dkern, C::LDS_BYTES, ddone);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(dkern, dim3(plan.dp_tiles), dim3(C::NT), C::LDS_BYTES, s, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
     hipLaunchKernelGGL(kern, dim3(plan.grid), dim3(C::NT), C::LDS_BYTES, s, a, plan);
     return hipGetLastError();
 }

@@ -242,6 +242,19 @@ __device__ inline float load_coherent(const float* p) {
     return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Buffer resource over [base, base + bytes) for raw buffer accesses (lanes outside the range
+// read zero and drop their stores).
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+constexpr int kCoherentAux = 16;   // cache policy sc1: device-coherent access
+
+// Four consecutive floats at byte offset off of a buffer, read device-coherently (16 bytes).
+__device__ inline floatx4 load4_coherent(__amdgpu_buffer_rsrc_t rs, int off) {
+    return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kCoherentAux));
+}
+
 // One chunk (tile rows R0 .. R0+EC-1) of the fused epilogue of tile (I, J), I <= J:
 //   Y = X^2 (from sY, or from the row-major BM x BM tile Y0 in memory if Y0 is set) plus the
 //   partial tiles parts[0..nparts-1] (part_stride floats apart, written by other workgroups and
@@ -253,7 +266,7 @@ __device__ inline float load_coherent(const float* p) {
 //   accumulate in tr, sq. Diagonal tiles keep only the upper triangle of X and A, and their lower
 //   half of hi/lo (or D) comes from the mirror pass, so every stored matrix is exactly symmetric.
 // Ends with a barrier (sY is free again).
-template <bool BF, class C>
+template <bool BF, class C, int UMAX>
 __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, int J,
                                  const float* __restrict__ Y0, const float* __restrict__ parts,
                                  size_t part_stride, int nparts, double& tr, double& sq) {
@@ -268,78 +281,99 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     const int64_t n = p.n;
     float* __restrict__ X = p.X;
     float* __restrict__ A = p.A;
-    constexpr int G = C::BM / 4;   // four-column groups per tile row
+    constexpr int G = C::BM / 4;                  // four-column groups per tile row
+    constexpr int PER = C::EC * G / C::NT;        // groups per thread in this chunk
+    constexpr int U = (PER % 4 == 0 && UMAX >= 4) ? 4 : (PER % 2 == 0 && UMAX >= 2) ? 2 : 1;
+    const uint32_t part_bytes = (uint32_t)(C::BM * C::BM * sizeof(float));
+    uint16_t* __restrict__ hout = p.hi_out;
+    uint16_t* __restrict__ lout = p.lo_out;
+    const bool load_a = last || dn != 0.0f;
 
-#pragma unroll 2
-    for (int e = tid; e < C::EC * G; e += C::NT) {
-        const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
-        if (diag && c + 3 < r) continue;   // entirely below the diagonal
-        const int loc = r * C::BM + c;
-        float* srow = sY + rl * C::LDY + c;
-        floatx4 y = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
-                       : *reinterpret_cast<const floatx4*>(srow);
-        for (int q = 0; q < nparts; ++q) {
-            const float* pp = parts + (size_t)q * part_stride + loc;
-            y[0] += load_coherent(pp);
-            y[1] += load_coherent(pp + 1);
-            y[2] += load_coherent(pp + 2);
-            y[3] += load_coherent(pp + 3);
-        }
-        const int64_t gr = I0 + r, gc = J0 + c;
-        const int64_t gi = gr * np + gc;
-        const floatx4 x = *reinterpret_cast<const floatx4*>(X + gi);
-        floatx4 xn;
+    // Row-major pass: groups of four consecutive columns, 16-byte accesses. The loads of U groups
+    // are issued before any of their stores, so that each thread keeps several requests in
+    // flight (the pass is bound by memory latency, not bandwidth, per workgroup).
+#pragma unroll 1
+    for (int b0 = 0; b0 < PER; b0 += U) {
+        floatx4 y[U], x[U], a[U];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) xn[k] = fmaf(ca, y[k], fmaf(cb, x[k], gr == gc + k ? cc : 0.0f));
-        const bool full = !diag || c >= r;
-        if (!last) {
-            if (full) {
-                *reinterpret_cast<floatx4*>(X + gi) = xn;
-                if (dn != 0.0f) {
-                    floatx4 a4 = *reinterpret_cast<const floatx4*>(A + gi);
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + (b0 + u) * C::NT;
+            const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
+            const int loc = r * C::BM + c;
+            const int64_t gi = (I0 + r) * np + J0 + c;
+            y[u] = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
+                      : *reinterpret_cast<const floatx4*>(sY + rl * C::LDY + c);
+            for (int q = 0; q < nparts; ++q) {
+                const floatx4 v = load4_coherent(make_rsrc(parts + (size_t)q * part_stride, part_bytes),
+                                                 loc * (int)sizeof(float));
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) a4[k] = fmaf(dn, xn[k], a4[k]);
-                    *reinterpret_cast<floatx4*>(A + gi) = a4;
-                }
-                u32x2 h, l;
-                split4<BF>(xn, h, l);
-                *reinterpret_cast<u32x2*>(p.hi_out + gi) = h;
-                *reinterpret_cast<u32x2*>(p.lo_out + gi) = l;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (c + k < r) continue;
-                    X[gi + k] = xn[k];
-                    if (dn != 0.0f) A[gi + k] = fmaf(dn, xn[k], A[gi + k]);
-                    uint16_t h, l;
-                    split16<BF>(xn[k], h, l);
-                    p.hi_out[gi + k] = h;
-                    p.lo_out[gi + k] = l;
-                }
+                for (int k = 0; k < 4; ++k) y[u][k] += v[k];
             }
-            *reinterpret_cast<floatx4*>(srow) = xn;
-        } else {
-            floatx4 out;
+            x[u] = *reinterpret_cast<const floatx4*>(X + gi);
+            if (load_a) a[u] = *reinterpret_cast<const floatx4*>(A + gi);
+        }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int64_t gck = gc + k;
-                double v = (double)A[gi + k] + (double)xn[k];
-                if (flip) v = (gr == gck ? 1.0 : 0.0) - v;
-                const float vf = ent ? 0.0f : (float)v;
-                const double vo = ent ? v : (double)vf;
-                if ((!diag || c + k >= r) && gr < n && gck < n) {
-                    if (gr == gck) tr += vo;
-                    sq += (gr == gck ? 1.0 : 2.0) * vo * vo;
-                    if (!ent) {
-                        if (p.out_mode == 0)
-                            reinterpret_cast<float*>(p.D)[gr * p.ldd + gck] = vf;
-                        else if (p.out_mode == 1)
-                            reinterpret_cast<double*>(p.D)[gr * p.ldd + gck] = (double)vf;
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + (b0 + u) * C::NT;
+            const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
+            if (diag && c + 3 < r) continue;   // entirely below the diagonal
+            float* srow = sY + rl * C::LDY + c;
+            const int64_t gr = I0 + r, gc = J0 + c;
+            const int64_t gi = gr * np + gc;
+            floatx4 xn;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                xn[k] = fmaf(ca, y[u][k], fmaf(cb, x[u][k], gr == gc + k ? cc : 0.0f));
+            const bool full = !diag || c >= r;
+            if (!last) {
+                if (full) {
+                    *reinterpret_cast<floatx4*>(X + gi) = xn;
+                    if (dn != 0.0f) {
+                        floatx4 a4;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) a4[k] = fmaf(dn, xn[k], a[u][k]);
+                        *reinterpret_cast<floatx4*>(A + gi) = a4;
+                    }
+                    u32x2 h, l;
+                    split4<BF>(xn, h, l);
+                    *reinterpret_cast<u32x2*>(hout + gi) = h;
+                    *reinterpret_cast<u32x2*>(lout + gi) = l;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (c + k < r) continue;
+                        X[gi + k] = xn[k];
+                        if (dn != 0.0f) A[gi + k] = fmaf(dn, xn[k], a[u][k]);
+                        uint16_t h, l;
+                        split16<BF>(xn[k], h, l);
+                        hout[gi + k] = h;
+                        lout[gi + k] = l;
                     }
                 }
-                out[k] = vf;
+                *reinterpret_cast<floatx4*>(srow) = xn;
+            } else {
+                floatx4 out;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t gck = gc + k;
+                    double v = (double)a[u][k] + (double)xn[k];
+                    if (flip) v = (gr == gck ? 1.0 : 0.0) - v;
+                    const float vf = ent ? 0.0f : (float)v;
+                    const double vo = ent ? v : (double)vf;
+                    if ((!diag || c + k >= r) && gr < n && gck < n) {
+                        if (gr == gck) tr += vo;
+                        sq += (gr == gck ? 1.0 : 2.0) * vo * vo;
+                        if (!ent) {
+                            if (p.out_mode == 0)
+                                reinterpret_cast<float*>(p.D)[gr * p.ldd + gck] = vf;
+                            else if (p.out_mode == 1)
+                                reinterpret_cast<double*>(p.D)[gr * p.ldd + gck] = (double)vf;
+                        }
+                    }
+                    out[k] = vf;
+                }
+                *reinterpret_cast<floatx4*>(srow) = out;
             }
-            *reinterpret_cast<floatx4*>(srow) = out;
         }
     }
     __syncthreads();
@@ -359,8 +393,8 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             if (!diag || r + 3 < c) {
                 u32x2 h, l;
                 split4<BF>(v, h, l);
-                *reinterpret_cast<u32x2*>(p.hi_out + oi) = h;
-                *reinterpret_cast<u32x2*>(p.lo_out + oi) = l;
+                *reinterpret_cast<u32x2*>(hout + oi) = h;
+                *reinterpret_cast<u32x2*>(lout + oi) = l;
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -417,8 +451,8 @@ __device__ inline void write_traces(const LayerArgs& p, double tr, double sq, fl
 
 // Fused epilogue of tile (I, J), I <= J, from the accumulators (which hold s X^2), plus optional
 // partial tiles of other workgroups (see epi_chunk). The accumulators go through sY EC rows at a
-// time.
-template <bool BF, class C>
+// time. UMAX bounds the groups whose loads a thread keeps in flight (register budget).
+template <bool BF, class C, int UMAX = 4>
 __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY, int I, int J,
                                 int tile_index, const float* __restrict__ parts = nullptr,
                                 size_t part_stride = 0, int nparts = 0) {
@@ -446,7 +480,7 @@ __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY
             }
         }
         __syncthreads();
-        epi_chunk<BF, C>(p, sY, R0, I, J, nullptr, parts, part_stride, nparts, tr, sq);
+        epi_chunk<BF, C, UMAX>(p, sY, R0, I, J, nullptr, parts, part_stride, nparts, tr, sq);
     }
     if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
@@ -482,14 +516,14 @@ __device__ inline void store_tile(const Acc<C>& acc, float* __restrict__ dst) {
 
 // Fused epilogue of tile (I, J), I <= J, reading X^2 from memory: Y = Y0 + parts[0] + ... +
 // parts[nparts-1] (Y0 row-major BM x BM, written by this workgroup; see epi_chunk).
-template <bool BF, class C>
+template <bool BF, class C, int UMAX = 4>
 __device__ inline void epilogue_mem(const LayerArgs& p, const float* __restrict__ Y0,
                                     const float* __restrict__ parts, size_t part_stride,
                                     int nparts, float* sY, int I, int J, int tile_index) {
     double tr = 0.0, sq = 0.0;
 #pragma unroll 1
     for (int ch = 0; ch < C::BM / C::EC; ++ch)
-        epi_chunk<BF, C>(p, sY, ch * C::EC, I, J, Y0, parts, part_stride, nparts, tr, sq);
+        epi_chunk<BF, C, UMAX>(p, sY, ch * C::EC, I, J, Y0, parts, part_stride, nparts, tr, sq);
     if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
 

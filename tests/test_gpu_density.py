@@ -245,3 +245,26 @@ def test_schedules_agree(api, sk_ws, paper_model, monkeypatch):
         monkeypatch.setenv("FE_SCHEDULE", sch)
         again = run(api, H, 0.05, 0.1, m, "fp16x2", ws=sk_ws)[0]
         assert np.array_equal(again, out[sch])
+
+
+def test_hybrid_schedule_agrees(api, paper_model, monkeypatch):
+    """n = 5700: 1035 upper tiles of 128 take two rounds of 512 workgroups, so the 128-tile
+    stream-K schedule runs one data-parallel round first, then stream-K over the remaining 523
+    tiles. Property check against the data-parallel schedule (the oracle would need minutes at
+    this size; both schedules are checked against it at smaller sizes)."""
+    m = paper_model
+    n = 5700
+    H = W.banded_decay(n, 8.0, 2.0, 31)
+    ws = api.Workspace(n)
+    out = {}
+    for sch in ("dp", "sk2"):
+        monkeypatch.setenv("FE_SCHEDULE", sch)
+        print(f"case hybrid n={n} schedule={sch}", flush=True)
+        out[sch] = run(api, H, 0.05, 0.1, m, "fp16x2", ws=ws)
+    d = np.max(np.abs(out["dp"][0] - out["sk2"][0]))
+    print(f"[hybrid] max |D_dp - D_sk2| = {d:.3e}", flush=True)
+    assert d < 1e-4
+    assert torch.equal(out["sk2"][4], out["sk2"][4].T)
+    assert out["sk2"][1] == pytest.approx(out["dp"][1], abs=1e-6 * n)
+    torch.cuda.synchronize()
+    ws.close()
