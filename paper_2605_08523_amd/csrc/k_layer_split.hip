@@ -51,13 +51,14 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2, 2
 k_layer_dp(LayerArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int T = (int)(p.np / C::BM);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);   // tiles [0, gridDim.x)
     int I, J;
-    tile_coords(blockIdx.x, T, I, J);
+    tile_coords(t, T, I, J);
     Acc<C> acc;
     zero(acc);
     kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
                  (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
-    epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, blockIdx.x);
+    epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 
 // Thread 0 waits until the workgroups of group g with indices jlo .. j-1 have published their

@@ -71,15 +71,46 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Tile t of the row-major walk over the upper triangle of a T x T tile grid.
+// Tile t of a blocked walk over the upper triangle of a T x T tile grid: blocks of B x B tiles
+// (bi, bj >= bi) in row-major block order, row-major inside a block (its upper part on the
+// diagonal). A run of consecutive tiles (what one XCD's workgroups hold at a time) then touches
+// fewer distinct row panels than a run of the plain row-major walk.
+constexpr int kTileBlock = 8;
 __device__ inline void tile_coords(int t, int T, int& I, int& J) {
-    int rem = t, i = 0;
-    while (rem >= T - i) {
-        rem -= T - i;
-        ++i;
+    constexpr int B = kTileBlock;
+    const int NB = (T + B - 1) / B;
+    int rem = t;
+    I = J = 0;
+    for (int bi = 0; bi < NB; ++bi) {
+        const int r0 = bi * B, h = T - r0 < B ? T - r0 : B;
+        for (int bj = bi; bj < NB; ++bj) {
+            const int c0 = bj * B, w = T - c0 < B ? T - c0 : B;
+            const int cnt = bj == bi ? h * (h + 1) / 2 : h * w;
+            if (rem < cnt) {
+                if (bj != bi) {
+                    I = r0 + rem / w;
+                    J = c0 + rem % w;
+                } else {
+                    int i = 0;
+                    while (rem >= h - i) {
+                        rem -= h - i;
+                        ++i;
+                    }
+                    I = r0 + i;
+                    J = r0 + i + rem;
+                }
+                return;
+            }
+            rem -= cnt;
+        }
     }
-    I = i;
-    J = i + rem;
+}
+
+// Tile of data-parallel workgroup b among ntiles: the hardware deals workgroups to the 8 XCDs
+// round-robin, so workgroup b runs on XCD b % 8; each XCD is given a contiguous run of tiles.
+__device__ inline int xcd_tile(int b, int ntiles) {
+    const int per = ntiles / 8;
+    return b < 8 * per ? (b % 8) * per + b / 8 : b;
 }
 
 // Compile-time shape of one kernel configuration.
