@@ -37,6 +37,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
+    p.add_argument("--workload", default="anderson4096",
+                   choices=["anderson4096", "batch1024", "large16384"],
+                   help="anderson4096: the headline line (default); batch1024: 1024 uneven "
+                        "matrices in one captured plan; large16384: one N = 16384 solve, "
+                        "density and entropy")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only a plain 1 GiB device-to-device copy, three times (the reference for "
                         "scaling the HBM byte counters)")
@@ -101,6 +106,10 @@ def main():
         torch.cuda.synchronize()
         print("copy calibration done: 3 copies of 1 GiB", flush=True)
         return
+    if args.workload == "batch1024":
+        return bench_batch(args, torch, api, models, workloads, dev)
+    if args.workload == "large16384":
+        return bench_large(args, torch, api, models, workloads, dev)
     m = models.load("mlsp2_L26_b1500_mu1third")
     c = workloads.config_anderson_4096()
     H = c["H"]
@@ -226,6 +235,105 @@ def main():
                                   "max_abs": float(np.max(np.abs(err))),
                                   "abs_dTrD": abs(float(trD) - ref["trD"]),
                                   "abs_dTrD2": abs(float(trD2) - ref["trD2"])}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, torch, api, models, workloads, dev):
+    """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (grouped per-layer launches in a
+    hipGraph), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
+    1e-5 bar on this batch: beta' reaches ~3700). Sampled items are checked against the CPU
+    oracle (eigendecomposition) in the cpu_baseline leg."""
+    import numpy as np
+    m = models.load("mlsp2_L40_b1e4_mu1third")
+    t0 = time.perf_counter()
+    items = workloads.batch_items(1024, 2000)
+    print(f"batch inputs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    mats = [dict(H=torch.from_numpy(it["H"]).to(dev), mu=it["mu"], kT=it["kT"]) for it in items]
+    prec = args.prec
+    plan = api.BatchPlan(mats, m, prec=prec)
+    ms = timed(plan.launch, args.steps, args.warmup, torch)
+    status = plan.status.cpu().numpy()
+    ns = np.array([it["n"] for it in items], dtype=np.float64)
+    flop = float(np.sum(m.L * 2.0 * ns ** 3))
+    out = {"metric": "density matrices/s (batch of 1024, N_b ~ U{64..768})",
+           "value": 1024 / (ms * 1e-3), "unit": "density matrices/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "dtype": "bf16" if prec == "bf16x2" else "f16",
+           "data": "synthetic",
+           "config": {"workload": "batch1024_banded_xi8_N64-768_seed2000", "items": 1024,
+                      "layers": m.L, "coefficients": "mlsp2_L40_b1e4_mu1third",
+                      "precision": prec},
+           "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
+           "status_nonzero": int(np.count_nonzero(status))}
+    if not args.no_cpu_baseline:
+        from oracle import fermi as F
+        order = np.argsort(ns)
+        sample = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+        errs = []
+        t0 = time.perf_counter()
+        for b in sample:
+            it = items[b]
+            ref = F.density(it["H"], it["mu"], it["kT"])
+            Dg = plan.D[b].double().cpu().numpy()
+            errs.append({"item": b, "N": it["n"],
+                         "fro_over_N": float(np.linalg.norm(Dg - ref["D"]) / it["n"]),
+                         "abs_dTrD": abs(float(plan.tr[b, 0]) - ref["trD"])})
+        dt = time.perf_counter() - t0
+        out["error_vs_oracle_sampled"] = errs
+        out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "density matrices/s",
+                               "kind": "oracle", "sample": "the smallest, median and largest "
+                               "item of the batch (eigendecomposition + assembly, FP64)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_large(args, torch, api, models, workloads, dev):
+    """One N = 16384 solve (h_ij = g_ij exp(-|i-j|/32), on-site U[-1,1], kT = 0.02, mu at 40%
+    filling), the 40-layer (1e4, 1/3) model: density (FP16x2) and entropy (FP16x2, theta_fermi
+    reused, alpha = 0.842704). mu is the midpoint of eigenvalues 0.4N and 0.4N + 1 (GPU
+    eigvalsh; input generation). Checked against the FP64 expansion on the GPU (the oracle's
+    eigendecomposition would take tens of minutes at this size)."""
+    import numpy as np
+    m = models.load("mlsp2_L40_b1e4_mu1third")
+    t0 = time.perf_counter()
+    c = workloads.config_large_banded()
+    n = c["H"].shape[0]
+    Hd = torch.from_numpy(c["H"]).to(dev)
+    del c["H"]
+    lam = torch.linalg.eigvalsh(Hd).cpu().numpy()
+    k = int(0.4 * n)
+    mu, kT = float(0.5 * (lam[k - 1] + lam[k])), c["kT"]
+    print(f"large input generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ws = api.Workspace(n)
+    D = torch.empty((n, n), dtype=torch.float32, device=dev)
+    mref = api.make_model(m.theta, m.beta0, m.mu0)
+    _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws,
+                                            want_info=True)
+    steps = max(1, min(args.steps, 5))
+    ms = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws),
+               steps, 1, torch)
+    ms_s = timed(lambda: api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws),
+                 steps, 1, torch)
+    S = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
+    D64, trD64, _, _ = api.expand_density(Hd, mu, kT, mref, prec="fp64", ws=ws,
+                                          out_dtype=torch.float64, want_info=True)
+    S64 = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec="fp64", ws=ws)[0])
+    torch.cuda.synchronize()
+    err = (D.double() - D64)
+    flop = m.L * 2.0 * n ** 3
+    out = {"metric": "density matrices/s (single N = 16384 solve)",
+           "value": 1000.0 / ms, "unit": "density matrices/s", "n_gpus": 1, "steps": steps,
+           "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+           "dtype": "f16" if args.prec == "fp16x2" else "bf16", "data": "synthetic",
+           "config": {"workload": "banded_xi32_N16384_seed4_kT0.02_fill0.4", "N": n,
+                      "layers": m.L, "coefficients": "mlsp2_L40_b1e4_mu1third",
+                      "precision": args.prec, "mu": mu, "beta_p": info["beta_p"]},
+           "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
+           "entropy_ms": ms_s,
+           "trD": float(trD), "trD_target": 0.4 * n,
+           "vs_fp64_expansion": {"fro_over_N": float(torch.linalg.norm(err).item() / n),
+                                 "max_abs": float(err.abs().max().item()),
+                                 "abs_dTrD": abs(float(trD) - float(trD64)),
+                                 "abs_dS": abs(S - S64), "S": S}}
     print(json.dumps(out), flush=True)
 
 
