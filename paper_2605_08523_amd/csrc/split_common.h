@@ -185,36 +185,63 @@ __device__ inline void kloop(const uint16_t* __restrict__ hin, const uint16_t* _
         }
     };
     const int frag_row = lane & 31, frag_k = (lane >> 5) * 8;
-    auto compute = [&](const uint16_t* buf) {
+    struct Frag {
+        u32x4 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+    };
+    auto ld = [&](const uint16_t* buf, int ks, Frag& f) {
         const uint16_t* sAh = buf;
         const uint16_t* sAl = sAh + C::BM * C::LDK;
         const uint16_t* sBh = sAl + C::BM * C::LDK;
         const uint16_t* sBl = sBh + C::BM * C::LDK;
 #pragma unroll
-        for (int ks = 0; ks < C::BK / 16; ++ks) {
-            u32x4 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+        for (int mb = 0; mb < C::MB; ++mb) {
+            const int o = (wm * C::WAVE_M + mb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
+            f.ah[mb] = *reinterpret_cast<const u32x4*>(sAh + o);
+            f.al[mb] = *reinterpret_cast<const u32x4*>(sAl + o);
+        }
 #pragma unroll
-            for (int mb = 0; mb < C::MB; ++mb) {
-                const int o = (wm * C::WAVE_M + mb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
-                ah[mb] = *reinterpret_cast<const u32x4*>(sAh + o);
-                al[mb] = *reinterpret_cast<const u32x4*>(sAl + o);
+        for (int nb = 0; nb < C::NB; ++nb) {
+            const int o = (wn * C::WAVE_N + nb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
+            f.bh[nb] = *reinterpret_cast<const u32x4*>(sBh + o);
+            f.bl[nb] = *reinterpret_cast<const u32x4*>(sBl + o);
+        }
+    };
+    auto mm = [&](const Frag& f) {
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) {
+            const u32x4 ahs = scale_hi<BF>(f.ah[mb]);
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb)
+                acc.v[mb][nb] = mfma3<BF>(ahs, f.ah[mb], f.al[mb], f.bh[nb], f.bl[nb], acc.v[mb][nb]);
+        }
+    };
+    // Small wave tiles read the next K step's fragments from LDS while the current step's
+    // MFMAs run (two fragment sets live); large ones keep one set (register budget). The
+    // scheduling barriers stop the compiler from hoisting further LDS reads, which would spill
+    // the accumulators.
+    constexpr int KS = C::BK / 16;
+    constexpr bool kPipe = C::MB * C::NB <= 4 && KS % 2 == 0;
+    auto compute = [&](const uint16_t* buf) {
+        if constexpr (kPipe) {
+            Frag f0, f1;
+            ld(buf, 0, f0);
+#pragma unroll
+            for (int ks = 0; ks < KS; ks += 2) {
+                ld(buf, ks + 1, f1);
+                mm(f0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (ks + 2 < KS) ld(buf, ks + 2, f0);
+                mm(f1);
+                __builtin_amdgcn_sched_barrier(0);
             }
+        } else {
 #pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) {
-                const int o = (wn * C::WAVE_N + nb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
-                bh[nb] = *reinterpret_cast<const u32x4*>(sBh + o);
-                bl[nb] = *reinterpret_cast<const u32x4*>(sBl + o);
+            for (int ks = 0; ks < KS; ++ks) {
+                Frag f;
+                ld(buf, ks, f);
+                mm(f);
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int mb = 0; mb < C::MB; ++mb) {
-                const u32x4 ahs = scale_hi<BF>(ah[mb]);
-#pragma unroll
-                for (int nb = 0; nb < C::NB; ++nb)
-                    acc.v[mb][nb] = mfma3<BF>(ahs, ah[mb], al[mb], bh[nb], bl[nb], acc.v[mb][nb]);
-            }
-            // keep one K step's operands live at a time (the scheduler would otherwise hoist the
-            // next step's LDS reads and spill the accumulators)
-            __builtin_amdgcn_sched_barrier(0);
         }
     };
 
