@@ -11,7 +11,7 @@ namespace fe {
 namespace {
 
 using namespace split;
-using CfgB = Cfg<128, 2, 2, 64, 64, 1>;   // same tile and K loop as the data-parallel single-matrix kernel
+using CfgB = Cfg<128, 2, 2, 64, 128, 1>;   // same tile and K loop as the data-parallel single-matrix kernel
 
 __device__ inline double wsum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -30,9 +30,9 @@ namespace {
 
 using namespace split;
 
-using CfgDP = Cfg<128, 2, 2, 64, 64, 1>;
+using CfgDP = Cfg<128, 2, 2, 64, 128, 1>;
 using CfgSK = Cfg<256, 2, 4, 32, 128, 2>;
-using CfgSK2 = Cfg<128, 2, 2, 64, 64, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
+using CfgSK2 = Cfg<128, 2, 2, 64, 128, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
 
 constexpr int kSpinLimit = 1 << 22;   // ~0.2 s of s_sleep before a wait gives up
 
@@ -161,11 +161,11 @@ k_layer_sk(LayerArgs p, SplitPlan sk) {
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else if constexpr (kRegEpi) {
                 wait_published(sk, g, NG, jlo, w);
-                epilogue<BF, C, 2>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
+                epilogue<BF, C, 1>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
             } else {
                 store_tile<BF, C, false>(acc, own);
                 wait_published(sk, g, NG, jlo, w);
-                epilogue_mem<BF, C, 2>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
+                epilogue_mem<BF, C, 1>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
             }
             it += kb1 - kb0;
         }

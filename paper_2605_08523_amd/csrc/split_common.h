@@ -347,28 +347,48 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     uint16_t* __restrict__ lout = p.lo_out;
     const bool load_a = last || dn != 0.0f;
 
-    // Row-major pass: groups of four consecutive columns, 16-byte accesses. The loads of U groups
-    // are issued before any of their stores, so that each thread keeps several requests in
-    // flight (the pass is bound by memory latency, not bandwidth, per workgroup).
-#pragma unroll 1
-    for (int b0 = 0; b0 < PER; b0 += U) {
-        floatx4 y[U], x[U], a[U];
+    // Row-major pass: groups of four consecutive columns, 16-byte accesses, in batches of U
+    // groups per thread. The loads of batch i + 1 are issued before the stores of batch i: the
+    // vector-memory counter is in order and counts stores too, so a wait for loads issued after
+    // a batch's stores would also wait for those stores to complete.
+    constexpr int NBATCH = PER / U;
+    struct Batch {
+        floatx4 y[U], x[U], a[U], p[U];
+    };
+    auto load_batch = [&](int b0, Batch& bt) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = tid + (b0 + u) * C::NT;
             const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
             const int loc = r * C::BM + c;
             const int64_t gi = (I0 + r) * np + J0 + c;
-            y[u] = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
-                      : *reinterpret_cast<const floatx4*>(sY + rl * C::LDY + c);
-            for (int q = 0; q < nparts; ++q) {
-                const floatx4 v = load4_coherent(make_rsrc(parts + (size_t)q * part_stride, part_bytes),
-                                                 loc * (int)sizeof(float));
+            bt.y[u] = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
+                         : *reinterpret_cast<const floatx4*>(sY + rl * C::LDY + c);
+            if (nparts > 0)
+                bt.p[u] = load4_coherent(make_rsrc(parts, part_bytes), loc * (int)sizeof(float));
+            bt.x[u] = *reinterpret_cast<const floatx4*>(X + gi);
+            if (load_a) bt.a[u] = *reinterpret_cast<const floatx4*>(A + gi);
+        }
+    };
+    auto finish_batch = [&](int b0, Batch& bt) {
+        floatx4* y = bt.y;
+        floatx4* x = bt.x;
+        floatx4* a = bt.a;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) y[u][k] += v[k];
+        for (int u = 0; u < U; ++u) {
+            if (nparts > 0) {
+                // parts in order: the first was loaded with the batch, the rest now
+                const int e = tid + (b0 + u) * C::NT;
+                const int loc = (R0 + e / G) * C::BM + (e % G) * 4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) y[u][k] += bt.p[u][k];
+                for (int q = 1; q < nparts; ++q) {
+                    const floatx4 v = load4_coherent(
+                        make_rsrc(parts + (size_t)q * part_stride, part_bytes), loc * (int)sizeof(float));
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) y[u][k] += v[k];
+                }
             }
-            x[u] = *reinterpret_cast<const floatx4*>(X + gi);
-            if (load_a) a[u] = *reinterpret_cast<const floatx4*>(A + gi);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -432,6 +452,18 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
                 }
                 *reinterpret_cast<floatx4*>(srow) = out;
             }
+        }
+    };
+    Batch bA, bB;
+    load_batch(0, bA);
+#pragma unroll
+    for (int bi = 0; bi < NBATCH; ++bi) {
+        if (bi & 1) {
+            if (bi + 1 < NBATCH) load_batch((bi + 1) * U, bA);
+            finish_batch(bi * U, bB);
+        } else {
+            if (bi + 1 < NBATCH) load_batch((bi + 1) * U, bB);
+            finish_batch(bi * U, bA);
         }
     }
     __syncthreads();
@@ -510,7 +542,7 @@ __device__ inline void write_traces(const LayerArgs& p, double tr, double sq, fl
 // Fused epilogue of tile (I, J), I <= J, from the accumulators (which hold s X^2), plus optional
 // partial tiles of other workgroups (see epi_chunk). The accumulators go through sY EC rows at a
 // time. UMAX bounds the groups whose loads a thread keeps in flight (register budget).
-template <bool BF, class C, int UMAX = 4>
+template <bool BF, class C, int UMAX = 8>
 __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY, int I, int J,
                                 int tile_index, const float* __restrict__ parts = nullptr,
                                 size_t part_stride = 0, int nparts = 0) {
@@ -574,7 +606,7 @@ __device__ inline void store_tile(const Acc<C>& acc, float* __restrict__ dst) {
 
 // Fused epilogue of tile (I, J), I <= J, reading X^2 from memory: Y = Y0 + parts[0] + ... +
 // parts[nparts-1] (Y0 row-major BM x BM, written by this workgroup; see epi_chunk).
-template <bool BF, class C, int UMAX = 4>
+template <bool BF, class C, int UMAX = 8>
 __device__ inline void epilogue_mem(const LayerArgs& p, const float* __restrict__ Y0,
                                     const float* __restrict__ parts, size_t part_stride,
                                     int nparts, float* sY, int I, int J, int tile_index) {
