@@ -208,9 +208,16 @@ def main():
             return (V * f) @ V.T
 
         ms_eig = timed(eig_density, 2, 1, torch)
+        # context for the MFMA fraction: the vendor FP16 GEMM (hipBLASLt via torch.matmul) on a
+        # plain N x N x N product with random operands, same box and session
+        ga = torch.randn(n, n, device=dev, dtype=torch.float16)
+        gb = torch.randn(n, n, device=dev, dtype=torch.float16).t().contiguous()
+        ms_gemm = timed(lambda: ga @ gb, 20, 3, torch)
+        del ga, gb
         out["gpu_baselines"] = {
             "fp64_recursion_torch_dgemm_ms": ms64,
             "fp64_eigh_plus_assembly_ms": ms_eig,
+            "vendor_fp16_gemm_tflops": 2.0 * n ** 3 / (ms_gemm * 1e-3) / 1e12,
             "speedup_vs_fp64_recursion": ms64 / ms,
             "speedup_vs_fp64_eigh": ms_eig / ms,
         }
