@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
     p.add_argument("--workload", default="anderson4096",
-                   choices=["anderson4096", "batch1024", "large16384"],
+                   choices=["anderson4096", "batch1024", "large16384", "filling4096"],
                    help="anderson4096: the headline line (default); batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
                         "density and entropy")
@@ -110,6 +110,8 @@ def main():
         return bench_batch(args, torch, api, models, workloads, dev)
     if args.workload == "large16384":
         return bench_large(args, torch, api, models, workloads, dev)
+    if args.workload == "filling4096":
+        return bench_filling(args, torch, api, models, workloads, dev)
     m = models.load("mlsp2_L26_b1500_mu1third")
     c = workloads.config_anderson_4096()
     H = c["H"]
@@ -341,6 +343,53 @@ def bench_large(args, torch, api, models, workloads, dev):
                                  "max_abs": float(err.abs().max().item()),
                                  "abs_dTrD": abs(float(trD) - float(trD64)),
                                  "abs_dS": abs(S - S64), "S": S}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_filling(args, torch, api, models, workloads, dev):
+    """The N = 4096 Anderson workload at half filling (Tr D = 2048) instead of a given mu: the
+    chemical potential by safeguarded Newton iterations (Sec. IV.3) from the midpoint of the
+    Gershgorin interval, each iterate one full expansion. Checked against the oracle's mu
+    (bisection on the eigenvalues) and density in the cpu_baseline leg."""
+    import numpy as np
+    m = models.load("mlsp2_L26_b1500_mu1third")
+    c = workloads.config_anderson_4096()
+    H = c["H"]
+    n = H.shape[0]
+    n_occ = 0.5 * n
+    Hd = torch.from_numpy(H).to(dev)
+    ws = api.Workspace(n)
+    D = torch.empty((n, n), dtype=torch.float32, device=dev)
+    mref = api.make_model(m.theta, m.beta0, m.mu0)
+    res = {}
+
+    def solve():
+        res["r"] = api.expand_density_filling(Hd, n_occ, c["kT"], mref, prec=args.prec, out=D,
+                                              ws=ws)
+    ms = timed(solve, max(1, min(args.steps, 10)), 1, torch)
+    _, mu, iters, tr, tr2, info = res["r"]
+    out = {"metric": "density matrices/s at a prescribed occupation (Newton mu)",
+           "value": 1000.0 / ms, "unit": "density matrices/s", "n_gpus": 1,
+           "steps": max(1, min(args.steps, 10)), "warmup": 1, "ms_per_step": ms,
+           "higher_is_better": True, "dtype": "f16" if args.prec == "fp16x2" else "bf16",
+           "data": "synthetic",
+           "config": {"workload": "anderson_cubic_16x16x16_periodic_N4096_t-1_W1_kT0.05_half_filling",
+                      "N": n, "n_occ": n_occ, "layers": m.L,
+                      "coefficients": "mlsp2_L26_b1500_mu1third", "precision": args.prec},
+           "newton_iterations": iters, "mu": mu, "abs_trD_minus_n_occ": abs(float(tr) - n_occ)}
+    if not args.no_cpu_baseline:
+        from oracle import fermi as F
+        t0 = time.perf_counter()
+        lam = np.linalg.eigvalsh(H)
+        mu_ref = F.mu_for_filling(lam, n_occ, c["kT"])
+        ref = F.density(H, mu_ref, c["kT"])
+        dt = time.perf_counter() - t0
+        err = D.double().cpu().numpy() - ref["D"]
+        out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
+                                  "abs_dmu": abs(mu - mu_ref)}
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "kind": "oracle",
+                               "sample": "the full matrix: eigenvalues, bisection for mu, then "
+                                         "eigendecomposition + assembly at that mu (FP64)"}
     print(json.dumps(out), flush=True)
 
 

@@ -49,7 +49,7 @@ extern "C" {
 #define FE_ERR_DOMAIN         -2   /* kT <= 0, or mu outside (eps_min, eps_max) */
 #define FE_ERR_HIP            -3   /* a HIP runtime call failed */
 #define FE_ERR_NONFINITE      -4   /* H holds a NaN or an infinity */
-#define FE_ERR_NO_CONVERGENCE -5   /* the coefficient fit did not reach its tolerance */
+#define FE_ERR_NO_CONVERGENCE -5   /* a fit or an iteration did not reach its tolerance */
 #define FE_ERR_WORKSPACE      -6   /* the workspace is too small for the request */
 #define FE_ERR_RANGE          -7   /* the model's layer values leave the 16-bit operand range */
 
@@ -111,6 +111,24 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
                       const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64, int64_t ldd,
                       double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
                       void* stream);
+
+/* Density matrix at a prescribed occupation (Sec. IV.3): the chemical potential solving
+ * Tr D(mu) = n_occ is found by Newton iterations with d Tr D / d mu = beta (Tr D - sum D_ij^2)
+ * (Eq. drho traced), each iterate one full expansion as in fe_expand_density; steps that leave
+ * the current bracket, or a vanishing derivative, fall back to bisection of the bracket (which
+ * starts as the Gershgorin interval of H).
+ * n_occ: target Tr D, in (0, n). mu_init: starting guess strictly inside the Gershgorin bounds,
+ *   or NaN for their midpoint. tol: stop when |Tr D - n_occ| <= tol. max_iter: >= 1.
+ * D, d_is_fp64, ldd, trD, trD2: as for fe_expand_density, for the final iterate.
+ * mu_out: host, the final mu. iters_out: host or NULL, expansions run. info: host or NULL, the
+ *   final iterate's rescale info. Synchronizes the stream once per iterate.
+ * Returns FE_ERR_NO_CONVERGENCE after max_iter iterates (D, mu_out hold the last one),
+ * FE_ERR_DOMAIN if mu_init lies outside the bounds, else as fe_expand_density. */
+int fe_expand_density_filling(const double* H, int64_t n, int64_t ldh, double n_occ, double kT,
+                              double mu_init, const fe_model* m, int32_t prec, double tol,
+                              int32_t max_iter, void* D, int32_t d_is_fp64, int64_t ldd,
+                              double* trD, double* trD2, double* mu_out, int32_t* iters_out,
+                              fe_rescale_info* info, fe_workspace* ws, void* stream);
 
 /* Entropy by Alg. 2 (steps 1-2 and 5) with entropy coefficients mS (trained at the same
  * (beta0, mu0) as the density model, or the density model itself) and rescale alpha

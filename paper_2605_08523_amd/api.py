@@ -63,6 +63,9 @@ SIGNATURES = {
                           C.POINTER(fe_rescale_info), _P, _P]),
     "fe_expand_density": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _P, _I32, _I64,
                                  _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_expand_density_filling": (_I32, [_P, _I64, _I64, _D, _D, _D, C.POINTER(fe_model), _I32, _D,
+                                         _I32, _P, _I32, _I64, _P, _P, C.POINTER(_D),
+                                         C.POINTER(_I32), C.POINTER(fe_rescale_info), _P, _P]),
     "fe_expand_entropy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _D, _I32, _P,
                                  C.POINTER(fe_rescale_info), _P, _P]),
     "fe_sp2_coeffs": (_I32, [_D, _I32, C.POINTER(_D)]),
@@ -222,6 +225,36 @@ def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=Non
         d = info.as_dict()
         d["rc"] = rc
     return out, (tr[0] if traces else None), (tr[1] if traces else None), d
+
+
+def expand_density_filling(H, n_occ: float, kT: float, model, prec: str = "fp16x2",
+                           mu_init: float | None = None, tol: float | None = None,
+                           max_iter: int = 50, out=None, out_dtype=None,
+                           ws: Workspace | None = None):
+    """fe_expand_density_filling. Returns (D, mu, iters, trD, trD2, info): the density matrix at
+    the chemical potential mu with Tr D = n_occ, found by safeguarded Newton iterations.
+    Default tol: 1e-6 n in the 16-bit and FP32 modes (the trace's own rounding noise is of that
+    order), 1e-10 n in FP64. Synchronizes the stream once per iterate."""
+    import torch
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    mr = _model_of(model)
+    if out is None:
+        out = torch.empty((n, n), dtype=out_dtype or torch.float32, device=H.device)
+    if out.dtype not in (torch.float32, torch.float64) or out.stride(1) != 1:
+        raise TypeError("out must be a row-major float32/float64 device tensor")
+    tr = torch.empty(2, dtype=torch.float64, device=H.device)
+    info = fe_rescale_info()
+    mu = C.c_double()
+    iters = C.c_int32()
+    _check(lib().fe_expand_density_filling(
+        C.c_void_p(H.data_ptr()), n, ldh, float(n_occ), float(kT),
+        float("nan") if mu_init is None else float(mu_init), C.byref(mr.struct), PREC[prec],
+        float((1e-10 if prec == "fp64" else 1e-6) * n if tol is None else tol), int(max_iter),
+        C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64), out.stride(0),
+        C.c_void_p(tr.data_ptr()), C.c_void_p(tr.data_ptr() + 8), C.byref(mu), C.byref(iters),
+        C.byref(info), ws.handle, _stream_ptr()))
+    return out, mu.value, iters.value, tr[0], tr[1], info.as_dict()
 
 
 def expand_entropy(H, mu: float, kT: float, model_s, alpha: float, prec: str = "fp16x2",

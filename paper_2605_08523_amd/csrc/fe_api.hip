@@ -257,6 +257,7 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
         e = hipMalloc(reinterpret_cast<void**>(&ws->bparts), 2 * fe::kMaxBoundsBlocks * sizeof(fe::BoundsPartial));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void**>(&ws->tparts), 2 * (size_t)fe::kMaxTiles * sizeof(fe::TracePartial));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->newton), 2 * sizeof(double));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ws->n_cu, hipDeviceAttributeMultiprocessorCount, ws->device);
     if (e == hipSuccess && max_n >= kStreamKMinN) {
         e = hipMalloc(reinterpret_cast<void**>(&ws->sk_partial), 2 * (size_t)ws->n_cu * 256 * 256 * sizeof(float));
@@ -291,6 +292,7 @@ int fe_workspace_destroy(fe_workspace* ws) {
     if (ws->params) (void)hipFree(ws->params);
     if (ws->bparts) (void)hipFree(ws->bparts);
     if (ws->tparts) (void)hipFree(ws->tparts);
+    if (ws->newton) (void)hipFree(ws->newton);
     if (ws->sk_partial) (void)hipFree(ws->sk_partial);
     if (ws->sk_flags) (void)hipFree(ws->sk_flags);
     if (ws->sk_err) (void)hipFree(ws->sk_err);
@@ -331,6 +333,68 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
                       void* stream) {
     return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
                          info, ws, static_cast<hipStream_t>(stream), 0);
+}
+
+int fe_expand_density_filling(const double* H, int64_t n, int64_t ldh, double n_occ, double kT,
+                              double mu_init, const fe_model* m, int32_t prec, double tol,
+                              int32_t max_iter, void* D, int32_t d_is_fp64, int64_t ldd,
+                              double* trD, double* trD2, double* mu_out, int32_t* iters_out,
+                              fe_rescale_info* info, fe_workspace* ws, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!mu_out) return fail(FE_ERR_ARG, "mu_out is NULL");
+    *mu_out = NAN;
+    if (iters_out) *iters_out = 0;
+    int rc = check_common(H, n, ldh, 0.0, kT, ws);
+    if (rc) return rc;
+    rc = check_model(m, "model");
+    if (rc) return rc;
+    if (!(n_occ > 0.0 && n_occ < (double)n)) return fail(FE_ERR_ARG, "n_occ must lie in (0, n)");
+    if (!(tol > 0.0) || max_iter < 1) return fail(FE_ERR_ARG, "tol must be > 0 and max_iter >= 1");
+
+    // Bracket: Tr D increases with mu, from ~0 below the Gershgorin interval to ~n above it.
+    FE_HIP(fe::launch_bounds_params(H, n, ldh, 0.0, kT, m->beta0, m->mu0, ws->bparts, ws->params, s));
+    FE_HIP(hipStreamSynchronize(s));
+    fe::Params p;
+    FE_HIP(hipMemcpy(&p, ws->params, sizeof(p), hipMemcpyDeviceToHost));
+    if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
+    double lo = p.emin, hi = p.emax;
+    if (!(hi > lo)) {   // H = c I: any mu is admissible; bracket a window of temperatures
+        lo = p.emin - 50.0 * kT;
+        hi = p.emax + 50.0 * kT;
+    }
+    double mu = isfinite(mu_init) ? mu_init : 0.5 * (lo + hi);
+    if (!(mu > lo && mu < hi)) return fail(FE_ERR_DOMAIN, "mu_init lies outside the Gershgorin bounds of H");
+
+    // Newton on Tr D(mu) = n_occ with d Tr D / d mu = (Tr D - sum D_ij^2) / kT (Sec. IV.3), kept
+    // inside the shrinking bracket: a step that leaves it, or a vanishing derivative (mu in a
+    // gap at low temperature), is replaced by bisection.
+    fe_rescale_info inf{};
+    double t[2] = {0.0, 0.0};
+    bool converged = false;
+    for (int it = 1; it <= max_iter; ++it) {
+        rc = run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, ws->newton,
+                           ws->newton + 1, nullptr, &inf, ws, s, 0);
+        if (rc < 0) return rc;
+        FE_HIP(hipMemcpy(t, ws->newton, sizeof(t), hipMemcpyDeviceToHost));
+        *mu_out = mu;
+        if (iters_out) *iters_out = it;
+        const double r = n_occ - t[0];
+        if (fabs(r) <= tol) {
+            converged = true;
+            break;
+        }
+        if (r > 0.0) lo = mu;
+        else hi = mu;
+        const double deriv = (t[0] - t[1]) / kT;
+        double next = deriv > 0.0 ? mu + r / deriv : NAN;
+        if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+        mu = next;
+    }
+    if (trD) FE_HIP(hipMemcpyAsync(trD, ws->newton, sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (trD2) FE_HIP(hipMemcpyAsync(trD2, ws->newton + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (info) *info = inf;
+    if (!converged) return fail(FE_ERR_NO_CONVERGENCE, "chemical potential not converged within max_iter");
+    return rc;
 }
 
 int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double kT,

@@ -22,6 +22,7 @@ struct fe_workspace {
     uint32_t* sk_flags = nullptr;                 // stream-K flags [n_cu]
     int* sk_err = nullptr;                        // stream-K wait failure flag
     uint32_t epoch = 0;                           // last stream-K launch epoch
+    double* newton = nullptr;                     // [2] traces of the current chemical-potential iterate
     // batch capacity
     int32_t max_batch = 0;
     int64_t batch_elems = 0;                      // sum of padded sizes squared it can hold

@@ -1,0 +1,90 @@
+"""GPU parity of fe_expand_density_filling (Sec. IV.3: Newton iterations for the chemical
+potential at a prescribed occupation) against the oracle: the exact mu from bisection of
+sum_i f(lambda_i; mu) = n_occ on the eigenvalues, and the exact density matrix at that mu."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fermi as F
+from paper_2605_08523_amd import models
+from paper_2605_08523_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_08523_amd import api as _api
+    _api.lib()
+    return _api
+
+
+CASES = [
+    # name, H, kT, filling, mu_init (None = midpoint of the Gershgorin interval), precision
+    ("anderson512_half", lambda: W.anderson_cubic(8, 7), 0.05, 0.5, None, "fp16x2"),
+    ("dense300_40pc_low_guess", lambda: W.random_dense(300, 5), 0.1, 0.4, -1.5, "fp16x2"),
+    ("banded700_30pc", lambda: W.banded_decay(700, 8.0, 2.0, 6), 0.2, 0.3, None, "bf16x2"),
+    ("dense128_half_fp64", lambda: W.random_dense(128, 0), 0.1, 0.5, None, "fp64"),
+]
+
+
+@pytest.mark.parametrize("name,make,kT,filling,mu_init,prec", CASES)
+def test_filling_against_oracle(api, paper_model, name, make, kT, filling, mu_init, prec):
+    m = paper_model
+    H = make()
+    n = H.shape[0]
+    n_occ = filling * n
+    print(f"case filling {name} n={n} n_occ={n_occ} prec={prec}", flush=True)
+    Hd = torch.from_numpy(H).cuda()
+    out_dtype = torch.float64 if prec == "fp64" else torch.float32
+    D, mu, iters, tr, tr2, info = api.expand_density_filling(Hd, n_occ, kT, m, prec=prec,
+                                                             mu_init=mu_init, out_dtype=out_dtype)
+    torch.cuda.synchronize()
+    ex_lam = np.linalg.eigvalsh(H)
+    mu_ref = F.mu_for_filling(ex_lam, n_occ, kT)
+    ref = F.density(H, mu_ref, kT)
+    Dn = D.double().cpu().numpy()
+    fro = np.linalg.norm(Dn - ref["D"]) / n
+    print(f"[filling {name}] iters={iters} mu={mu:.10f} mu_ref={mu_ref:.10f} "
+          f"|TrD-n_occ|={abs(float(tr) - n_occ):.2e} |dD|_F/N={fro:.3e}", flush=True)
+    assert abs(float(tr) - n_occ) <= (1e-10 if prec == "fp64" else 1e-6) * n
+    assert iters <= 12
+    # mu differs from the exact one by the model error over dN/dmu = beta sum f(1 - f)
+    f = 1.0 / (1.0 + np.exp((ex_lam - mu_ref) / kT))
+    dn_dmu = np.sum(f * (1 - f)) / kT
+    assert abs(mu - mu_ref) <= 1e-5 * n / dn_dmu + 1e-9
+    assert fro <= 1e-5
+    assert torch.equal(D, D.T)
+
+
+def test_filling_in_a_gap(api, paper_model):
+    """Low temperature, n_occ an integer inside a spectral gap: Tr D is flat around the answer
+    (vanishing derivative); the bracket keeps the iteration inside the gap."""
+    n, nb = 200, 80
+    H, lam = W.gapped_spectrum(n, nb, 0.4, 9)
+    Hd = torch.from_numpy(H).cuda()
+    D, mu, iters, tr, tr2, info = api.expand_density_filling(Hd, float(nb), 0.005, paper_model,
+                                                             prec="fp16x2", tol=1e-6)
+    torch.cuda.synchronize()
+    print(f"[filling gap] iters={iters} mu={mu:.6f} TrD={float(tr):.9f}", flush=True)
+    assert -0.2 < mu < 0.2
+    assert abs(float(tr) - nb) <= 1e-6
+    # idempotent: the projector onto the occupied states
+    assert abs(float(tr) - float(tr2)) < 1e-4
+
+
+def test_filling_errors(api, paper_model):
+    H = torch.from_numpy(W.random_dense(128, 1)).cuda()
+    with pytest.raises(api.FeError) as e:
+        api.expand_density_filling(H, 0.0, 0.1, paper_model)
+    assert e.value.code == -1
+    with pytest.raises(api.FeError) as e:
+        api.expand_density_filling(H, 64.0, 0.1, paper_model, mu_init=1e3)
+    assert e.value.code == -2
+    with pytest.raises(api.FeError) as e:
+        api.expand_density_filling(H, 64.0, 0.1, paper_model, mu_init=-2.0, max_iter=1, tol=1e-12)
+    assert e.value.code == -5
