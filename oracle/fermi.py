@@ -90,6 +90,19 @@ def entropy(H: np.ndarray, mu: float, kT: float) -> float:
     return float(entropy_fn(lam, mu, kT).sum())
 
 
+def free_energy(H: np.ndarray, mu: float, kT: float) -> float:
+    """Electronic free energy with the spin factor, G = 2 Tr[g(H)] (Sec. III.B, Eq. free_energy):
+    g(x) = f(x)(x - mu) - kT s(x), summed over the eigenvalues (k_B = 1, T = kT)."""
+    lam = np.linalg.eigvalsh(np.asarray(H, dtype=np.float64))
+    f = fermi(lam, mu, kT)
+    return float(2.0 * np.sum(f * (lam - mu) - kT * entropy_fn(lam, mu, kT)))
+
+
+def observable(D: np.ndarray, A: np.ndarray) -> float:
+    """Expectation value <A> = 2 Tr(D A) of a symmetric observable (Sec. II.A, Eq. observables)."""
+    return float(2.0 * np.sum(np.asarray(D, dtype=np.float64) * np.asarray(A, dtype=np.float64)))
+
+
 def mu_for_filling(lam, n_target: float, kT: float, tol: float = 1e-12) -> float:
     """Chemical potential with sum_i f(lambda_i; mu) = n_target, by bisection.
 

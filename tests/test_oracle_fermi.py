@@ -171,3 +171,49 @@ def test_mu_for_filling():
     lam = np.linalg.eigvalsh(W.random_dense(128, 0))
     mu = F.mu_for_filling(lam, 64.0, 0.1)
     assert F.fermi(lam, mu, 0.1).sum() == pytest.approx(64.0, abs=1e-9)
+
+
+def test_free_energy_diagonal_closed_form():
+    """Diagonal H: G = 2 sum_i [f_i (h_i - mu) - kT s_i] with f, s written out directly."""
+    h = np.array([-1.3, -0.2, 0.05, 0.9, 2.0])
+    mu, kT = 0.1, 0.07
+    f = 1.0 / (1.0 + np.exp((h - mu) / kT))
+    s = -f * np.log(f) - (1 - f) * np.log(1 - f)
+    G = 2.0 * np.sum(f * (h - mu) - kT * s)
+    assert F.free_energy(np.diag(h), mu, kT) == pytest.approx(G, rel=1e-13, abs=1e-14)
+
+
+def test_free_energy_matrix_form_and_mu_derivative():
+    """The eigenvalue form equals the matrix form 2 Tr[D (H - mu I)] - 2 kT S (Sec. III.B), and
+    dG/dmu = -2 Tr D (d/dmu of f (x - mu) - kT s(x) is -f), by central differences."""
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((40, 40))
+    H = (A + A.T) / 8.0
+    mu, kT = 0.07, 0.15
+    d = F.density(H, mu, kT)
+    G_matrix = 2.0 * np.sum(d["D"] * H) - 2.0 * mu * d["trD"] - 2.0 * kT * d["S"]
+    G = F.free_energy(H, mu, kT)
+    assert G == pytest.approx(G_matrix, rel=1e-12, abs=1e-12)
+    h = 1e-5
+    dG = (F.free_energy(H, mu + h, kT) - F.free_energy(H, mu - h, kT)) / (2 * h)
+    assert dG == pytest.approx(-2.0 * d["trD"], rel=1e-8)
+
+
+def test_free_energy_zero_temperature_limit():
+    """kT -> 0 with a gap at mu: G -> 2 sum_{lam < mu} (lam - mu) (the entropy term vanishes)."""
+    lam = np.array([-1.0, -0.6, -0.2, 0.3, 0.8])
+    H = np.diag(lam)
+    G0 = 2.0 * np.sum(lam[lam < 0.0] - 0.0)
+    assert F.free_energy(H, 0.0, 1e-4) == pytest.approx(G0, abs=1e-12)
+
+
+def test_observable_is_twice_the_frobenius_product():
+    rng = np.random.default_rng(12)
+    H = rng.standard_normal((6, 6)); H = H + H.T
+    A = rng.standard_normal((6, 6)); A = A + A.T
+    D = F.density(H, 0.0, 0.5)["D"]
+    assert F.observable(D, A) == pytest.approx(2.0 * np.trace(D @ A), rel=1e-13)
+    # <H> at mu is the internal energy part of G: G = <H> - 2 mu Tr D - 2 kT S
+    d = F.density(H, 0.0, 0.5)
+    assert F.free_energy(H, 0.0, 0.5) == pytest.approx(
+        F.observable(d["D"], H) - 2 * 0.0 * d["trD"] - 2 * 0.5 * d["S"], rel=1e-12)
