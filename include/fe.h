@@ -137,6 +137,24 @@ int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double
                       const fe_model* mS, double alpha, int32_t prec, double* S,
                       fe_rescale_info* info, fe_workspace* ws, void* stream);
 
+/* Expectation value <A> = 2 Tr(D A) = 2 sum_ij D_ij A_ij of a symmetric observable (Sec. II.A,
+ * Eq. observables; the 2 counts spin). D: device n x n (ld ldd), float32 (d_is_fp64 = 0) or
+ * float64; A: device float64 n x n (ld lda). out: device float64 scalar. FP64 accumulation in a
+ * fixed order (deterministic). Asynchronous on stream. */
+int fe_observable(const void* D, int32_t d_is_fp64, int64_t ldd, const double* A, int64_t lda,
+                  int64_t n, double* out, fe_workspace* ws, void* stream);
+
+/* Electronic free energy G = 2 Tr[D (H - mu I)] - 2 kT S (Sec. III.B; S per spin channel,
+ * k_B = 1): the entropy expansion with mS (or m when mS is NULL) and rescale alpha, the density
+ * expansion with m, then the Frobenius product Tr[D H] of D as stored. D: device output as for
+ * fe_expand_density, or NULL (then the workspace holds it, in float32). G: device float64 scalar; S, trD:
+ * device float64 scalars or NULL. info: as for fe_expand_density (the density expansion's).
+ * Asynchronous on stream unless info is given. */
+int fe_free_energy(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                   const fe_model* m, const fe_model* mS, double alpha, int32_t prec, void* D,
+                   int32_t d_is_fp64, int64_t ldd, double* G, double* S, double* trD,
+                   fe_rescale_info* info, fe_workspace* ws, void* stream);
+
 /* ---- batches of matrices of uneven size ------------------------------------------------ */
 
 /* One Hamiltonian of a batch. All pointers are device memory owned by the caller. */

@@ -66,6 +66,9 @@ SIGNATURES = {
     "fe_expand_density_filling": (_I32, [_P, _I64, _I64, _D, _D, _D, C.POINTER(fe_model), _I32, _D,
                                          _I32, _P, _I32, _I64, _P, _P, C.POINTER(_D),
                                          C.POINTER(_I32), C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_observable": (_I32, [_P, _I32, _I64, _P, _I64, _I64, _P, _P, _P]),
+    "fe_free_energy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), C.POINTER(fe_model), _D,
+                              _I32, _P, _I32, _I64, _P, _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
     "fe_expand_entropy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _D, _I32, _P,
                                  C.POINTER(fe_rescale_info), _P, _P]),
     "fe_sp2_coeffs": (_I32, [_D, _I32, C.POINTER(_D)]),
@@ -255,6 +258,48 @@ def expand_density_filling(H, n_occ: float, kT: float, model, prec: str = "fp16x
         C.c_void_p(tr.data_ptr()), C.c_void_p(tr.data_ptr() + 8), C.byref(mu), C.byref(iters),
         C.byref(info), ws.handle, _stream_ptr()))
     return out, mu.value, iters.value, tr[0], tr[1], info.as_dict()
+
+
+def observable(D, A, ws: Workspace | None = None):
+    """fe_observable: <A> = 2 Tr(D A) as a 0-d float64 device tensor (asynchronous)."""
+    import torch
+    n = D.shape[0]
+    if D.dim() != 2 or D.shape[1] != n or D.stride(1) != 1 or D.dtype not in (torch.float32, torch.float64):
+        raise TypeError("D must be a square row-major float32/float64 device tensor")
+    if A.shape != D.shape or A.dtype != torch.float64 or A.stride(1) != 1 or not A.is_cuda:
+        raise TypeError("A must be a row-major float64 device tensor of D's shape")
+    ws = ws or workspace(n)
+    out = torch.empty((), dtype=torch.float64, device=D.device)
+    _check(lib().fe_observable(C.c_void_p(D.data_ptr()), int(D.dtype == torch.float64), D.stride(0),
+                               C.c_void_p(A.data_ptr()), A.stride(0), n, C.c_void_p(out.data_ptr()),
+                               ws.handle, _stream_ptr()))
+    return out
+
+
+def free_energy(H, mu: float, kT: float, model, model_s=None, alpha: float = 1.0,
+                prec: str = "fp16x2", out=None, want_D: bool = False, out_dtype=None,
+                ws: Workspace | None = None):
+    """fe_free_energy. Returns (G, S, trD, D): 0-d float64 device tensors G = 2 Tr[D (H - mu I)]
+    - 2 kT S, S and Tr D, and D (``out``, or a new tensor of out_dtype, float32 by default, when
+    want_D). Tr[D H] is formed from D as stored (float32 D rounds it)."""
+    import torch
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    mr = _model_of(model)
+    ms = _model_of(model_s) if model_s is not None else None
+    if out is None and want_D:
+        out = torch.empty((n, n), dtype=out_dtype or torch.float32, device=H.device)
+    if out is not None and (out.dtype not in (torch.float32, torch.float64) or out.stride(1) != 1):
+        raise TypeError("out must be a row-major float32/float64 device tensor")
+    sc = torch.empty(3, dtype=torch.float64, device=H.device)
+    _check(lib().fe_free_energy(
+        C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct),
+        C.byref(ms.struct) if ms is not None else None, float(alpha), PREC[prec],
+        C.c_void_p(out.data_ptr() if out is not None else 0),
+        int(out is not None and out.dtype == torch.float64), out.stride(0) if out is not None else 0,
+        C.c_void_p(sc.data_ptr()), C.c_void_p(sc.data_ptr() + 8), C.c_void_p(sc.data_ptr() + 16),
+        None, ws.handle, _stream_ptr()))
+    return sc[0], sc[1], sc[2], out
 
 
 def expand_entropy(H, mu: float, kT: float, model_s, alpha: float, prec: str = "fp16x2",

@@ -258,6 +258,8 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void**>(&ws->tparts), 2 * (size_t)fe::kMaxTiles * sizeof(fe::TracePartial));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->newton), 2 * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void**>(&ws->dots), (fe::kMaxDotBlocks + 3) * sizeof(double));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ws->n_cu, hipDeviceAttributeMultiprocessorCount, ws->device);
     if (e == hipSuccess && max_n >= kStreamKMinN) {
         e = hipMalloc(reinterpret_cast<void**>(&ws->sk_partial), 2 * (size_t)ws->n_cu * 256 * 256 * sizeof(float));
@@ -293,6 +295,7 @@ int fe_workspace_destroy(fe_workspace* ws) {
     if (ws->bparts) (void)hipFree(ws->bparts);
     if (ws->tparts) (void)hipFree(ws->tparts);
     if (ws->newton) (void)hipFree(ws->newton);
+    if (ws->dots) (void)hipFree(ws->dots);
     if (ws->sk_partial) (void)hipFree(ws->sk_partial);
     if (ws->sk_flags) (void)hipFree(ws->sk_flags);
     if (ws->sk_err) (void)hipFree(ws->sk_err);
@@ -394,6 +397,47 @@ int fe_expand_density_filling(const double* H, int64_t n, int64_t ldh, double n_
     if (trD2) FE_HIP(hipMemcpyAsync(trD2, ws->newton + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
     if (info) *info = inf;
     if (!converged) return fail(FE_ERR_NO_CONVERGENCE, "chemical potential not converged within max_iter");
+    return rc;
+}
+
+int fe_observable(const void* D, int32_t d_is_fp64, int64_t ldd, const double* A, int64_t lda,
+                  int64_t n, double* out, fe_workspace* ws, void* stream) {
+    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
+    if (!D || !A || !out) return fail(FE_ERR_ARG, "D, A and out must be non-NULL");
+    if (n < 1 || ldd < n || lda < n) return fail(FE_ERR_ARG, "n < 1 or a leading dimension < n");
+    FE_HIP(fe::launch_dot(D, d_is_fp64, ldd, A, lda, n, ws->dots, 0, 0.0, 0.0, nullptr, nullptr,
+                          out, static_cast<hipStream_t>(stream)));
+    return FE_OK;
+}
+
+int fe_free_energy(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                   const fe_model* m, const fe_model* mS, double alpha, int32_t prec, void* D,
+                   int32_t d_is_fp64, int64_t ldd, double* G, double* S, double* trD,
+                   fe_rescale_info* info, fe_workspace* ws, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!G) return fail(FE_ERR_ARG, "G is NULL");
+    int rc = check_common(H, n, ldh, mu, kT, ws);
+    if (rc) return rc;
+    double* dS = ws->dots + fe::kMaxDotBlocks;
+    double* dtr = dS + 1;
+    // entropy first on slot 1; afterwards that slot holds D when the caller passes none
+    rc = run_expansion(H, n, ldh, mu, kT, mS ? mS : m, prec, alpha, 1, nullptr, 0, 0, nullptr,
+                       nullptr, dS, nullptr, ws, s, 1);
+    if (rc < 0) return rc;
+    void* Dw = D;
+    int64_t ldw = ldd;
+    int w64 = d_is_fp64;
+    if (!Dw) {
+        Dw = ws->slot[1];
+        ldw = n;
+        w64 = 0;
+    }
+    rc = run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, Dw, w64, ldw, dtr, dtr + 1, nullptr,
+                       info, ws, s, 0);
+    if (rc < 0) return rc;
+    FE_HIP(fe::launch_dot(Dw, w64, ldw, H, ldh, n, ws->dots, 1, mu, kT, dtr, dS, G, s));
+    if (S) FE_HIP(hipMemcpyAsync(S, dS, sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (trD) FE_HIP(hipMemcpyAsync(trD, dtr, sizeof(double), hipMemcpyDeviceToDevice, s));
     return rc;
 }
 

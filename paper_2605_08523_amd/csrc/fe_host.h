@@ -23,6 +23,7 @@ struct fe_workspace {
     int* sk_err = nullptr;                        // stream-K wait failure flag
     uint32_t epoch = 0;                           // last stream-K launch epoch
     double* newton = nullptr;                     // [2] traces of the current chemical-potential iterate
+    double* dots = nullptr;                       // [kMaxDotBlocks + 3] Frobenius-product partials, S, trD
     // batch capacity
     int32_t max_batch = 0;
     int64_t batch_elems = 0;                      // sum of padded sizes squared it can hold

@@ -214,6 +214,14 @@ hipError_t launch_bwd_elem(const BwdArgs& a, int nblocks, double* grad4, hipStre
 hipError_t launch_fwd_out(const float* hist, int64_t n, int L, const MatTheta& th, float* P,
                           hipStream_t s);
 
+// Frobenius product sum_ij D_ij A_ij over n x n (D float32 or float64, A float64) into at most
+// kMaxDotBlocks partials, then one fixed-order reduction: mode 0 writes out = 2 sum (Eq.
+// observables); mode 1 writes the free energy out = 2 (sum - mu *trD) - 2 kT *S.
+constexpr int kMaxDotBlocks = 2048;
+hipError_t launch_dot(const void* D, int d_is_fp64, int64_t ldd, const double* A, int64_t lda,
+                      int64_t n, double* partials, int mode, double mu, double kT,
+                      const double* trD, const double* S, double* out, hipStream_t s);
+
 // Deterministic reduction of tile partials: out_tr = sum tr, out_sq = sum sq; if entropy,
 // out_S = 4 ln2 (sum tr - sum sq).
 hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,
