@@ -179,6 +179,8 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         const int T = (int)(np / tile);
         npart = T * (T + 1) / 2;
         if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
+        std::vector<float> d_old, d_new;
+        pair_accumulator_terms(m->L, dval, d_old, d_new);
         for (int i = 0; i < m->L; ++i) {
             fe::LayerArgs la{};
             la.np = np; la.n = n;
@@ -186,7 +188,8 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             la.hi_out = b.hi[(i + 1) & 1]; la.lo_out = b.lo[(i + 1) & 1];
             la.X = b.X; la.A = b.A;
             la.a = (float)th[4 * i]; la.b = (float)th[4 * i + 1]; la.c = (float)th[4 * i + 2];
-            la.d_next = (i + 1 < m->L) ? (float)dval(i + 1) : 0.0f;
+            la.d_old = d_old[i];
+            la.d_new = d_new[i];
             la.last = (i + 1 == m->L);
             la.out_mode = out_mode; la.entropy = entropy; la.D = D; la.ldd = ldd;
             la.P = P; la.partials = tp;

@@ -42,6 +42,8 @@ int enqueue_pass(fe_workspace* ws, int count, int total_tiles, int64_t max_np, c
     };
     if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, m->beta0, m->mu0, ws->bparams, s));
     FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, m->mu0, dval(0), bf, s));
+    std::vector<float> d_old, d_new;
+    pair_accumulator_terms(m->L, dval, d_old, d_new);
     for (int i = 0; i < m->L; ++i) {
         fe::BatchLayerArgs q{};
         q.mats = ws->bmats;
@@ -50,7 +52,8 @@ int enqueue_pass(fe_workspace* ws, int count, int total_tiles, int64_t max_np, c
         q.a = (float)th[4 * i];
         q.b = (float)th[4 * i + 1];
         q.c = (float)th[4 * i + 2];
-        q.d_next = (i + 1 < m->L) ? (float)dval(i + 1) : 0.0f;
+        q.d_old = d_old[i];
+        q.d_new = d_new[i];
         q.last = (i + 1 == m->L);
         q.entropy = entropy;
         q.P = ws->bparams;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "fe_internal.h"
 
@@ -60,6 +61,26 @@ inline int hip_fail(hipError_t e, const char* what) {
 
 inline constexpr int kMaxLayers = 4096;
 inline constexpr double kDSkip = 1e-8;   // accumulator weights below this are skipped (Sec. V.A)
+
+// Accumulator schedule of the 16-bit layer kernels. The recursion adds d_j X_j for j = 1 .. L-1
+// (d_0 X_0 is formed by the rescale; X_L is the output). Layer i's epilogue sees X_i (its input)
+// and X_{i+1} (its output), so each term can be added by one of two layers; terms are paired,
+// A += d_j X_j + d_{j+1} X_{j+1} at layer j, which halves the layers that read and write A.
+// dv(j) is d_j after the skip rule; d_old[i], d_new[i] are layer i's weights of X_i, X_{i+1}.
+template <class DV>
+inline void pair_accumulator_terms(int L, DV dv, std::vector<float>& d_old, std::vector<float>& d_new) {
+    d_old.assign(L, 0.0f);
+    d_new.assign(L, 0.0f);
+    for (int j = 1; j < L;) {
+        if (dv(j) == 0.0) {
+            ++j;
+            continue;
+        }
+        d_old[j] = (float)dv(j);
+        if (j + 1 < L) d_new[j] = (float)dv(j + 1);
+        j += 2;
+    }
+}
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 

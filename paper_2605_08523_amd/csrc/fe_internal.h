@@ -79,7 +79,7 @@ struct LayerArgs {
     float* X;               // FP32 master (upper triangle maintained), in place
     float* A;               // accumulator (upper triangle maintained), in place
     float a, b, c;          // this layer's coefficients
-    float d_next;           // next layer's accumulator weight (0 = skip)
+    float d_old, d_new;     // A += d_old X + d_new X' (X the layer's input, X' its output; 0 0 = skip)
     int last;               // 1 on the last layer
     int out_mode;           // last layer: 0 = D float32, 1 = D float64, 2 = traces only
     int entropy;            // last layer: partials hold U traces for S (no D written)
@@ -168,7 +168,7 @@ struct BatchLayerArgs {
     const BatchMat* mats;
     int count;
     int parity;             // hi/lo buffer read by this layer
-    float a, b, c, d_next;
+    float a, b, c, d_old, d_new;
     int last, entropy;
     const Params* P;
     TracePartial* partials;

@@ -168,7 +168,8 @@ k_batch_layer(BatchLayerArgs q) {
     p.a = q.a;
     p.b = q.b;
     p.c = q.c;
-    p.d_next = q.d_next;
+    p.d_old = q.d_old;
+    p.d_new = q.d_new;
     p.last = q.last;
     p.entropy = q.entropy;
     p.D = m.D;

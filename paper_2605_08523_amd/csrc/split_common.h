@@ -317,7 +317,7 @@ __device__ inline floatx4 load4_coherent(__amdgpu_buffer_rsrc_t rs, int off) {
 //   Y = X^2 (from sY, or from the row-major BM x BM tile Y0 in memory if Y0 is set) plus the
 //   partial tiles parts[0..nparts-1] (part_stride floats apart, written by other workgroups and
 //   read device-coherently, added in this order);
-//   X' = a Y + b X + c delta_ij;  A += d_next X';  write the FP32 master and the next layer's
+//   X' = a Y + b X + c delta_ij;  A += d_old X + d_new X';  write the FP32 master and the next layer's
 //   hi/lo for the tile (row-major pass, four columns per thread) and its mirror (transposed pass
 //   through sY, four rows per thread). On the last layer: D = A + X' (delta_ij - D if flipped)
 //   written to the tile and its mirror, or (entropy) U = A + X' traced only; FP64 trace sums
@@ -332,7 +332,8 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     const int64_t np = p.np;
     const int64_t I0 = (int64_t)I * C::BM, J0 = (int64_t)J * C::BM;
     const bool diag = (I == J);
-    const float ca = p.a, cb = p.b, cc = p.c, dn = p.d_next;
+    const float ca = p.a, cb = p.b, cc = p.c, dold = p.d_old, dnew = p.d_new;
+    const bool upd = dold != 0.0f || dnew != 0.0f;
     const bool last = p.last != 0;
     const bool ent = p.entropy != 0;
     const int flip = (last && !ent) ? p.P->flipped : 0;
@@ -345,7 +346,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     const uint32_t part_bytes = (uint32_t)(C::BM * C::BM * sizeof(float));
     uint16_t* __restrict__ hout = p.hi_out;
     uint16_t* __restrict__ lout = p.lo_out;
-    const bool load_a = last || dn != 0.0f;
+    const bool load_a = last || upd;
 
     // Row-major pass: groups of four consecutive columns, 16-byte accesses, in batches of U
     // groups per thread. The loads of batch i + 1 are issued before the stores of batch i: the
@@ -406,10 +407,11 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             if (!last) {
                 if (full) {
                     *reinterpret_cast<floatx4*>(X + gi) = xn;
-                    if (dn != 0.0f) {
+                    if (upd) {
                         floatx4 a4;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) a4[k] = fmaf(dn, xn[k], a[u][k]);
+                        for (int k = 0; k < 4; ++k)
+                            a4[k] = fmaf(dnew, xn[k], fmaf(dold, x[u][k], a[u][k]));
                         *reinterpret_cast<floatx4*>(A + gi) = a4;
                     }
                     u32x2 h, l;
@@ -421,7 +423,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
                     for (int k = 0; k < 4; ++k) {
                         if (c + k < r) continue;
                         X[gi + k] = xn[k];
-                        if (dn != 0.0f) A[gi + k] = fmaf(dn, xn[k], a[u][k]);
+                        if (upd) A[gi + k] = fmaf(dnew, xn[k], fmaf(dold, x[u][k], a[u][k]));
                         uint16_t h, l;
                         split16<BF>(xn[k], h, l);
                         hout[gi + k] = h;
@@ -434,7 +436,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int64_t gck = gc + k;
-                    double v = (double)a[u][k] + (double)xn[k];
+                    double v = (double)a[u][k] + (double)dold * (double)x[u][k] + (double)xn[k];
                     if (flip) v = (gr == gck ? 1.0 : 0.0) - v;
                     const float vf = ent ? 0.0f : (float)v;
                     const double vo = ent ? v : (double)vf;
