@@ -274,6 +274,20 @@ def bench_batch(args, torch, api, models, workloads, dev):
                       "precision": prec},
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "status_nonzero": int(np.count_nonzero(status))}
+    # the same batch over the model bank: each matrix runs the fewest layers valid for it
+    bank_names = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third",
+                  "mlsp2_L26_b1500_mu1third", "mlsp2_L40_b1e4_mu1third"]
+    bank = [models.load(x) for x in bank_names]
+    plan.close()
+    bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)
+    ms_b = timed(bplan.launch, args.steps, args.warmup, torch)
+    Ls = np.array([bank[k].L for k in bplan.chosen], dtype=np.float64)
+    out["model_bank"] = {
+        "value": 1024 / (ms_b * 1e-3), "unit": "density matrices/s", "ms_per_step": ms_b,
+        "models": bank_names,
+        "items_per_model": [int(np.sum(bplan.chosen == k)) for k in range(len(bank))],
+        "tflops_algorithmic": float(np.sum(Ls * 2.0 * ns ** 3)) / (ms_b * 1e-3) / 1e12,
+        "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy()))}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         order = np.argsort(ns)
@@ -284,9 +298,12 @@ def bench_batch(args, torch, api, models, workloads, dev):
             it = items[b]
             ref = F.density(it["H"], it["mu"], it["kT"])
             Dg = plan.D[b].double().cpu().numpy()
+            Db = bplan.D[b].double().cpu().numpy()
             errs.append({"item": b, "N": it["n"],
                          "fro_over_N": float(np.linalg.norm(Dg - ref["D"]) / it["n"]),
-                         "abs_dTrD": abs(float(plan.tr[b, 0]) - ref["trD"])})
+                         "abs_dTrD": abs(float(plan.tr[b, 0]) - ref["trD"]),
+                         "bank_model": bank_names[int(bplan.chosen[b])],
+                         "bank_fro_over_N": float(np.linalg.norm(Db - ref["D"]) / it["n"])})
         dt = time.perf_counter() - t0
         out["error_vs_oracle_sampled"] = errs
         out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "density matrices/s",

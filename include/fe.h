@@ -186,6 +186,19 @@ typedef struct fe_batch_plan fe_batch_plan;
 int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_model* m,
                          const fe_model* mS, double alpha, int32_t prec, int32_t* status,
                          fe_workspace* ws, fe_batch_plan** plan);
+/* A plan over a bank of models (the model-bank selection of Sec. IV.1's region of validity,
+ * Eq. conditions): item i runs the bank model with the fewest layers whose region contains its
+ * (beta', mu'), i.e. beta' <= beta0 min(mu0/mu', (1 - mu0)/(1 - mu')) with beta' and mu' from
+ * the item's Gershgorin bounds (ties: the larger beta0); an item no model covers runs the model
+ * with the widest region and reports FE_WARN_BETA_CLAMPED. bank: host array of nbank models.
+ * with_entropy: also compute S[i] with each item's model (Sec. III.B reuse of the Fermi
+ * coefficients) and rescale alpha. chosen: host int32[count] or NULL, receives the model index
+ * per item. Synchronizes once (the bounds are read back to choose); otherwise as
+ * fe_batch_plan_create. */
+int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const fe_model* bank,
+                              int32_t nbank, int32_t with_entropy, double alpha, int32_t prec,
+                              int32_t* status, int32_t* chosen, fe_workspace* ws,
+                              fe_batch_plan** plan);
 int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
 int fe_batch_plan_destroy(fe_batch_plan* plan);
 

@@ -348,6 +348,8 @@ class fe_batch_item(C.Structure):
 SIGNATURES.update({
     "fe_batch_plan_create": (_I32, [C.POINTER(fe_batch_item), _I32, C.POINTER(fe_model),
                                     C.POINTER(fe_model), _D, _I32, _P, _P, C.POINTER(_P)]),
+    "fe_batch_plan_create_bank": (_I32, [C.POINTER(fe_batch_item), _I32, C.POINTER(fe_model), _I32,
+                                         _I32, _D, _I32, _P, C.POINTER(_I32), _P, C.POINTER(_P)]),
     "fe_batch_plan_launch": (_I32, [_P, _P]),
     "fe_batch_plan_destroy": (_I32, [_P]),
     "fe_batched_expand": (_I32, [C.POINTER(fe_batch_item), _I32, C.POINTER(fe_model),
@@ -360,10 +362,15 @@ class BatchPlan:
 
     Each entry of `mats` is a dict with keys H (float64 device tensor), mu, kT. Outputs are
     allocated here: D (float32, or float64 with d_dtype), traces tr[b] = (Tr D, sum D_ij^2), S[b]
-    (entropy, when model_s is given) and status[b] (int32 rescale status)."""
+    (entropy, when model_s is given or with_entropy with a bank) and status[b] (int32 rescale
+    status).
+
+    `model` is one model, or a list of models (a bank, fe_batch_plan_create_bank): then every
+    matrix runs the bank model with the fewest layers whose region of validity contains its
+    (beta', mu'), and `chosen[b]` is that model's index in the list."""
 
     def __init__(self, mats, model, prec="fp16x2", model_s=None, alpha=1.0, ws=None,
-                 want_D=True, d_dtype=None):
+                 want_D=True, d_dtype=None, with_entropy=False):
         import torch
         self.count = len(mats)
         dev = mats[0]["H"].device
@@ -383,19 +390,32 @@ class BatchPlan:
                                    D.data_ptr() if want_D else None, n if want_D else 0,
                                    int(d_dtype == torch.float64),
                                    self.tr.data_ptr() + 16 * b, self.tr.data_ptr() + 16 * b + 8,
-                                   self.S.data_ptr() + 8 * b if model_s is not None else None)
+                                   self.S.data_ptr() + 8 * b
+                                   if (model_s is not None or with_entropy) else None)
             np_ = -(-n // 128) * 128
             elems += np_ * np_
         self._items = arr
         self.ws = ws or Workspace(128, max_batch=self.count, batch_elems=elems)
-        self._m = _model_of(model)
-        self._ms = _model_of(model_s) if model_s is not None else None
         p = C.c_void_p()
-        _check(lib().fe_batch_plan_create(arr, self.count, C.byref(self._m.struct),
-                                          C.byref(self._ms.struct) if self._ms else None,
-                                          float(alpha), PREC[prec],
-                                          C.c_void_p(self.status.data_ptr()), self.ws.handle,
-                                          C.byref(p)))
+        self.chosen = None
+        if isinstance(model, (list, tuple)):
+            self._bank = [_model_of(x) for x in model]
+            structs = (fe_model * len(self._bank))(*[x.struct for x in self._bank])
+            self._bank_structs = structs
+            chosen = (C.c_int32 * self.count)()
+            _check(lib().fe_batch_plan_create_bank(
+                arr, self.count, structs, len(self._bank), int(bool(with_entropy)), float(alpha),
+                PREC[prec], C.c_void_p(self.status.data_ptr()), chosen, self.ws.handle,
+                C.byref(p)))
+            self.chosen = np.array(chosen[:], dtype=np.int32)
+        else:
+            self._m = _model_of(model)
+            self._ms = _model_of(model_s) if model_s is not None else None
+            _check(lib().fe_batch_plan_create(arr, self.count, C.byref(self._m.struct),
+                                              C.byref(self._ms.struct) if self._ms else None,
+                                              float(alpha), PREC[prec],
+                                              C.c_void_p(self.status.data_ptr()), self.ws.handle,
+                                              C.byref(p)))
         self._p = p
 
     def launch(self):

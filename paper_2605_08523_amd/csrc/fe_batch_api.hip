@@ -1,7 +1,10 @@
 // Host side of the batched expansion: a plan lays the batch out in the workspace arena
-// (matrices sorted by decreasing padded size), uploads the per-matrix descriptors once and
-// captures the whole launch sequence (bounds, rescale, L grouped layers, reductions, and the
-// entropy pass when an entropy model is given) into one hipGraph that each launch replays.
+// (matrices sorted by decreasing layer count, then decreasing padded size), uploads the
+// per-matrix descriptors and the coefficient tables once and captures the whole launch sequence
+// (bounds, rescale, the grouped layers, reductions, and the entropy pass when requested) into one
+// hipGraph that each launch replays. With a model bank every matrix runs the model with the
+// fewest layers whose region of validity (Eq. conditions) contains its (beta', mu').
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -16,10 +19,10 @@ using namespace fehost;
 struct fe_batch_plan {
     uint64_t gen = 0;       // workspace layout generation this plan was built for
     int count = 0;
-    int total_tiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     fe_workspace* ws = nullptr;
+    void* tables = nullptr; // device coefficient tables of both passes
 };
 
 namespace {
@@ -32,89 +35,75 @@ int check_item(const fe_batch_item& it, int i) {
     return FE_OK;
 }
 
-// Enqueues one expansion pass (density or entropy) of the whole batch on `s`.
-int enqueue_pass(fe_workspace* ws, int count, int total_tiles, int64_t max_np, const fe_model* m,
-                 double alpha, int entropy, int bf, int prec, int32_t* status, hipStream_t s) {
-    const double* th = m->theta;
-    auto dval = [&](int i) {
-        const double d = th[4 * i + 3];
-        return (prec != FE_PREC_FP64 && fabs(d) < kDSkip) ? 0.0 : d;
-    };
-    if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, m->beta0, m->mu0, ws->bparams, s));
-    FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, m->mu0, dval(0), bf, s));
-    std::vector<float> d_old, d_new;
-    pair_accumulator_terms(m->L, dval, d_old, d_new);
-    for (int i = 0; i < m->L; ++i) {
+// Host image of one pass's coefficient tables (layout of fe::BatchCoef).
+struct PassTables {
+    std::vector<float> coef;
+    std::vector<int32_t> L;
+    std::vector<float> d0;
+    int max_L = 0;
+};
+
+PassTables make_tables(const std::vector<const fe_model*>& ms, int prec) {
+    PassTables t;
+    for (const fe_model* m : ms) t.max_L = std::max(t.max_L, (int)m->L);
+    t.coef.assign(ms.size() * t.max_L * 8, 0.0f);
+    for (size_t k = 0; k < ms.size(); ++k) {
+        const fe_model* m = ms[k];
+        const double* th = m->theta;
+        auto dval = [&](int i) {
+            const double d = th[4 * i + 3];
+            return (prec != FE_PREC_FP64 && fabs(d) < kDSkip) ? 0.0 : d;
+        };
+        std::vector<float> d_old, d_new;
+        pair_accumulator_terms(m->L, dval, d_old, d_new);
+        for (int l = 0; l < m->L; ++l) {
+            float* c = &t.coef[(k * t.max_L + l) * 8];
+            c[0] = (float)th[4 * l];
+            c[1] = (float)th[4 * l + 1];
+            c[2] = (float)th[4 * l + 2];
+            c[3] = d_old[l];
+            c[4] = d_new[l];
+        }
+        t.L.push_back(m->L);
+        t.d0.push_back((float)dval(0));
+    }
+    return t;
+}
+
+// Enqueues one expansion pass (density or entropy) of the whole batch on `s`. active[l] is the
+// number of tiles of the matrices with more than l layers (a prefix of the sorted batch).
+int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoef& cf,
+                 const std::vector<int>& active, double alpha, int entropy, int bf,
+                 int32_t* status, hipStream_t s) {
+    if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, s));
+    FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, cf, bf, s));
+    for (int l = 0; l < cf.max_L; ++l) {
+        if (active[l] == 0) break;
         fe::BatchLayerArgs q{};
         q.mats = ws->bmats;
         q.count = count;
-        q.parity = i & 1;
-        q.a = (float)th[4 * i];
-        q.b = (float)th[4 * i + 1];
-        q.c = (float)th[4 * i + 2];
-        q.d_old = d_old[i];
-        q.d_new = d_new[i];
-        q.last = (i + 1 == m->L);
+        q.parity = l & 1;
+        q.layer = l;
         q.entropy = entropy;
+        q.cf = cf;
         q.P = ws->bparams;
         q.partials = ws->btparts;
-        FE_HIP(fe::launch_batch_layer(q, total_tiles, bf, s));
+        FE_HIP(fe::launch_batch_layer(q, active[l], bf, s));
     }
     FE_HIP(fe::launch_batch_reduce(ws->bmats, count, ws->btparts, ws->bparams, entropy, status, s));
     return FE_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_model* m,
-                         const fe_model* mS, double alpha, int32_t prec, int32_t* status,
-                         fe_workspace* ws, fe_batch_plan** out) {
-    if (!out) return fail(FE_ERR_ARG, "out is NULL");
-    *out = nullptr;
-    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
-    if (!items || count < 1) return fail(FE_ERR_ARG, "empty batch");
-    if (count > ws->max_batch) return fail(FE_ERR_WORKSPACE, "batch larger than the workspace's max_batch");
-    int rc = check_model(m, "model");
-    if (rc) return rc;
-    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2 and BF16x2 modes");
-    if (layer_range(m, 1.0) > 16.0) return fail(FE_ERR_RANGE, "layer values exceed the 16-bit operand range");
-    if (mS) {
-        rc = check_model(mS, "entropy model");
-        if (rc) return rc;
-        if (mS->beta0 != m->beta0 || mS->mu0 != m->mu0)
-            return fail(FE_ERR_ARG, "the entropy model must share (beta0, mu0) with the density model");
-        if (!(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
-        if (layer_range(mS, alpha) > 16.0)
-            return fail(FE_ERR_RANGE, "entropy layer values exceed the 16-bit operand range");
-    }
-    for (int i = 0; i < count; ++i) {
-        rc = check_item(items[i], i);
-        if (rc) return rc;
-    }
+// Descriptors of the batch in the arena, in `order`; model[i] is item i's model index.
+std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<int>& order,
+                                 const std::vector<int>& model,
+                                 const std::vector<const fe_model*>& ms, fe_workspace* ws,
+                                 int64_t* tiles_out, int64_t* max_np_out) {
     const int64_t bt = fe::batch_tile();
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return items[a].n > items[b].n; });
-    std::vector<fe::BatchMat> mats(count);
-    int64_t elems = 0, tiles = 0, max_np = 0;
-    for (int k = 0; k < count; ++k) {
-        const fe_batch_item& it = items[order[k]];
-        const int64_t np = round_up(it.n, bt);
-        const int64_t T = np / bt;
-        elems += np * np;
-        tiles += T * (T + 1) / 2;
-        max_np = std::max(max_np, np);
-    }
-    if (elems > ws->batch_elems) return fail(FE_ERR_WORKSPACE, "batch exceeds the workspace arena");
-    if (tiles > ws->batch_tiles || tiles > (int64_t)0x7fffffff)
-        return fail(FE_ERR_WORKSPACE, "batch has too many tiles for the workspace");
+    std::vector<fe::BatchMat> mats(order.size());
     char* arena = static_cast<char*>(ws->arena);
-    int64_t off = 0, t0 = 0;
-    for (int k = 0; k < count; ++k) {
+    int64_t off = 0, t0 = 0, max_np = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
         const fe_batch_item& it = items[order[k]];
         fe::BatchMat& bm = mats[k];
         memset(&bm, 0, sizeof(bm));
@@ -126,6 +115,9 @@ int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_mod
         bm.np = np;
         bm.mu = it.mu;
         bm.kT = it.kT;
+        bm.model = model[order[k]];
+        bm.beta0 = ms[bm.model]->beta0;
+        bm.mu0 = ms[bm.model]->mu0;
         bm.X = reinterpret_cast<float*>(arena + off * 16);
         bm.A = bm.X + e;
         uint16_t* h = reinterpret_cast<uint16_t*>(bm.A + e);
@@ -143,25 +135,118 @@ int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_mod
         bm.tile0 = (int32_t)t0;
         off += (int64_t)e;
         t0 += (np / bt) * (np / bt + 1) / 2;
+        max_np = std::max(max_np, np);
     }
+    *tiles_out = t0;
+    *max_np_out = max_np;
+    return mats;
+}
+
+int check_batch(const fe_batch_item* items, int count, fe_workspace* ws) {
+    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
+    if (!items || count < 1) return fail(FE_ERR_ARG, "empty batch");
+    if (count > ws->max_batch) return fail(FE_ERR_WORKSPACE, "batch larger than the workspace's max_batch");
+    const int64_t bt = fe::batch_tile();
+    int64_t elems = 0, tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_item(items[i], i);
+        if (rc) return rc;
+        const int64_t np = round_up(items[i].n, bt), T = np / bt;
+        elems += np * np;
+        tiles += T * (T + 1) / 2;
+    }
+    if (elems > ws->batch_elems) return fail(FE_ERR_WORKSPACE, "batch exceeds the workspace arena");
+    if (tiles > ws->batch_tiles || tiles > (int64_t)0x7fffffff)
+        return fail(FE_ERR_WORKSPACE, "batch has too many tiles for the workspace");
+    return FE_OK;
+}
+
+// Builds and captures a plan: item i runs model dens[model[i]] (and ent[model[i]] for the
+// entropy pass when ent is non-empty).
+int build_plan(const fe_batch_item* items, int count, const std::vector<int>& model,
+               const std::vector<const fe_model*>& dens, const std::vector<const fe_model*>& ent,
+               double alpha, int32_t prec, int32_t* status, fe_workspace* ws,
+               fe_batch_plan** out) {
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int la = dens[model[a]]->L, lb = dens[model[b]]->L;
+        if (la != lb) return la > lb;
+        return items[a].n > items[b].n;
+    });
+    int64_t tiles = 0, max_np = 0;
+    std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, &tiles, &max_np);
+    const PassTables td = make_tables(dens, prec);
+    PassTables te;
+    if (!ent.empty()) te = make_tables(ent, prec);
+    // active tiles per layer (the sorted order makes them a prefix in both passes)
+    auto active_tiles = [&](const PassTables& t) {
+        std::vector<int> act(t.max_L, 0);
+        for (int l = 0; l < t.max_L; ++l) {
+            int64_t a = 0;
+            bool prefix = true;
+            for (int k = 0; k < count; ++k) {
+                const bool on = t.L[mats[k].model] > l;
+                if (!on) prefix = false;
+                else if (!prefix) return std::vector<int>();   // not a prefix
+                else a = (k + 1 < count) ? mats[k + 1].tile0 : tiles;
+            }
+            act[l] = (int)a;
+        }
+        return act;
+    };
+    const std::vector<int> act_d = active_tiles(td);
+    const std::vector<int> act_e = ent.empty() ? std::vector<int>() : active_tiles(te);
+    if (act_d.empty() || (!ent.empty() && act_e.empty()))
+        return fail(FE_ERR_ARG, "entropy and density models must order the batch the same way");
     FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
 
     fe_batch_plan* plan = new fe_batch_plan();
-    plan->gen = ++ws->batch_gen;   // earlier plans on this workspace become stale
     plan->count = count;
-    plan->total_tiles = (int)tiles;
     plan->ws = ws;
-    hipStream_t cs;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    // device tables: [density coef | density L | density d0 | entropy ...], 256-byte aligned parts
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t cd = al(td.coef.size() * 4), ld = al(td.L.size() * 4), dd = al(td.d0.size() * 4);
+    const size_t ce = al(te.coef.size() * 4), le = al(te.L.size() * 4), de = al(te.d0.size() * 4);
+    hipError_t e = hipMalloc(&plan->tables, cd + ld + dd + ce + le + de + 256);
     if (e != hipSuccess) {
         delete plan;
+        return hip_fail(e, "hipMalloc (batch tables)");
+    }
+    char* base = static_cast<char*>(plan->tables);
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    fe::BatchCoef cfd{reinterpret_cast<const float*>(base), reinterpret_cast<const int32_t*>(base + cd),
+                      reinterpret_cast<const float*>(base + cd + ld), td.max_L};
+    const size_t eo = cd + ld + dd;
+    fe::BatchCoef cfe{reinterpret_cast<const float*>(base + eo),
+                      reinterpret_cast<const int32_t*>(base + eo + ce),
+                      reinterpret_cast<const float*>(base + eo + ce + le), te.max_L};
+    e = up(0, td.coef.data(), td.coef.size() * 4);
+    if (e == hipSuccess) e = up(cd, td.L.data(), td.L.size() * 4);
+    if (e == hipSuccess) e = up(cd + ld, td.d0.data(), td.d0.size() * 4);
+    if (e == hipSuccess) e = up(eo, te.coef.data(), te.coef.size() * 4);
+    if (e == hipSuccess) e = up(eo + ce, te.L.data(), te.L.size() * 4);
+    if (e == hipSuccess) e = up(eo + ce + le, te.d0.data(), te.d0.size() * 4);
+    if (e != hipSuccess) {
+        fe_batch_plan_destroy(plan);
+        return hip_fail(e, "hipMemcpy (batch tables)");
+    }
+    plan->gen = ++ws->batch_gen;   // earlier plans on this workspace become stale
+    hipStream_t cs;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fe_batch_plan_destroy(plan);
         return hip_fail(e, "hipStreamCreate");
     }
+    int rc = FE_OK;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int bf = prec == FE_PREC_BF16X2;
     if (e == hipSuccess) {
-        rc = enqueue_pass(ws, count, (int)tiles, max_np, m, 1.0, 0, bf, prec, status, cs);
-        if (rc == FE_OK && mS) rc = enqueue_pass(ws, count, (int)tiles, max_np, mS, alpha, 1, bf, prec, status, cs);
+        rc = enqueue_pass(ws, count, max_np, cfd, act_d, 1.0, 0, bf, status, cs);
+        if (rc == FE_OK && !ent.empty())
+            rc = enqueue_pass(ws, count, max_np, cfe, act_e, alpha, 1, bf, status, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         plan->graph = g;
@@ -182,6 +267,111 @@ int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_mod
     return FE_OK;
 }
 
+int check_16bit_model(const fe_model* m, double alpha, const char* what) {
+    int rc = check_model(m, what);
+    if (rc) return rc;
+    if (layer_range(m, alpha) > 16.0)
+        return fail(FE_ERR_RANGE, std::string(what) + ": layer values exceed the 16-bit operand range");
+    return FE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_model* m,
+                         const fe_model* mS, double alpha, int32_t prec, int32_t* status,
+                         fe_workspace* ws, fe_batch_plan** out) {
+    if (!out) return fail(FE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch(items, count, ws);
+    if (rc) return rc;
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
+        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2 and BF16x2 modes");
+    rc = check_16bit_model(m, 1.0, "model");
+    if (rc) return rc;
+    if (mS) {
+        if (!(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
+        rc = check_16bit_model(mS, alpha, "entropy model");
+        if (rc) return rc;
+        if (mS->beta0 != m->beta0 || mS->mu0 != m->mu0)
+            return fail(FE_ERR_ARG, "the entropy model must share (beta0, mu0) with the density model");
+    }
+    std::vector<int> model(count, 0);
+    std::vector<const fe_model*> dens{m}, ent;
+    if (mS) ent.push_back(mS);
+    return build_plan(items, count, model, dens, ent, alpha, prec, status, ws, out);
+}
+
+int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const fe_model* bank,
+                              int32_t nbank, int32_t with_entropy, double alpha, int32_t prec,
+                              int32_t* status, int32_t* chosen, fe_workspace* ws,
+                              fe_batch_plan** out) {
+    if (!out) return fail(FE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch(items, count, ws);
+    if (rc) return rc;
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
+        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2 and BF16x2 modes");
+    if (!bank || nbank < 1) return fail(FE_ERR_ARG, "empty model bank");
+    if (with_entropy && !(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
+    std::vector<const fe_model*> ms;
+    for (int k = 0; k < nbank; ++k) {
+        rc = check_16bit_model(&bank[k], 1.0, "bank model");
+        if (rc) return rc;
+        if (with_entropy) {
+            rc = check_16bit_model(&bank[k], alpha, "bank model (entropy)");
+            if (rc) return rc;
+        }
+        ms.push_back(&bank[k]);
+    }
+    // (beta', mu') of every item from its Gershgorin bounds: one bounds pass, synchronized.
+    std::vector<int> provisional(count, 0), order(count);
+    std::iota(order.begin(), order.end(), 0);
+    int64_t tiles = 0, max_np = 0;
+    std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, &tiles, &max_np);
+    FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
+    FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, nullptr));
+    std::vector<fe::Params> P(count);
+    FE_HIP(hipMemcpy(P.data(), ws->bparams, sizeof(fe::Params) * count, hipMemcpyDeviceToHost));
+    // Smallest layer count whose region of validity (beta' <= beta_max(mu'), Eq. conditions)
+    // contains the item; if none does, the model with the largest beta_max (the item is clamped
+    // and reports FE_WARN_BETA_CLAMPED).
+    std::vector<int> model(count, 0);
+    for (int i = 0; i < count; ++i) {
+        const double lo = P[i].emin, hi = P[i].emax, width = hi - lo;
+        int best = -1, widest = 0;
+        double widest_b = -1.0;
+        const bool usable = isfinite(lo) && isfinite(hi) && items[i].kT > 0.0;
+        const bool degenerate = usable && !(width > 1e-300 * fmax(1.0, fabs(hi)));
+        double mu_p = 0.5, beta_p = 0.0;
+        if (usable && !degenerate) {
+            mu_p = (hi - items[i].mu) / width;
+            if (mu_p > 0.5) mu_p = 1.0 - mu_p;
+            beta_p = width / items[i].kT;
+        }
+        for (int k = 0; k < nbank; ++k) {
+            const fe_model* m = ms[k];
+            const double bmax = (mu_p > 0.0 && mu_p <= 0.5)
+                                    ? fmin(m->mu0 / mu_p, (1.0 - m->mu0) / (1.0 - mu_p)) * m->beta0
+                                    : 0.0;
+            if (bmax > widest_b) {
+                widest_b = bmax;
+                widest = k;
+            }
+            const bool fits = !usable || degenerate || beta_p <= bmax;
+            if (fits && (best < 0 || m->L < ms[best]->L ||
+                         (m->L == ms[best]->L && m->beta0 > ms[best]->beta0)))
+                best = k;
+        }
+        model[i] = best >= 0 ? best : widest;
+        if (chosen) chosen[i] = model[i];
+    }
+    std::vector<const fe_model*> ent;
+    if (with_entropy) ent = ms;
+    return build_plan(items, count, model, ms, ent, alpha, prec, status, ws, out);
+}
+
 int fe_batch_plan_launch(fe_batch_plan* plan, void* stream) {
     if (!plan || !plan->exec) return fail(FE_ERR_ARG, "invalid plan");
     if (plan->gen != plan->ws->batch_gen)
@@ -194,6 +384,7 @@ int fe_batch_plan_destroy(fe_batch_plan* plan) {
     if (!plan) return FE_OK;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->tables) (void)hipFree(plan->tables);
     delete plan;
     return FE_OK;
 }

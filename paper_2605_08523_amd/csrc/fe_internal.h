@@ -150,6 +150,7 @@ struct BatchMat {
     const double* H;
     int64_t n, ldh, np;
     double mu, kT;
+    double beta0, mu0;      // training point of the model this matrix runs with
     float* X;
     float* A;
     uint16_t* hi[2];
@@ -162,23 +163,35 @@ struct BatchMat {
     double* trD2;
     double* S;
     int32_t tile0;          // first tile of this matrix in the grouped grid
-    int32_t pad;
+    int32_t model;          // index of its model in the pass's coefficient tables
+};
+// Coefficients of one pass (density or entropy) for every model of a batch: layer l of model k
+// at coef[(k * max_L + l) * 8 + {0, 1, 2, 3, 4}] = a, b, c, d_old, d_new (accumulator terms
+// paired as in the single-matrix kernels); model k has L[k] layers and initial weight d0[k].
+struct BatchCoef {
+    const float* coef;
+    const int32_t* L;
+    const float* d0;
+    int max_L;
 };
 struct BatchLayerArgs {
     const BatchMat* mats;
     int count;
     int parity;             // hi/lo buffer read by this layer
-    float a, b, c, d_old, d_new;
-    int last, entropy;
+    int layer;
+    int entropy;
+    BatchCoef cf;
     const Params* P;
     TracePartial* partials;
 };
 int batch_tile();
-hipError_t launch_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P,
-                               hipStream_t s);
+// Bounds and rescale parameters of every matrix with its own (beta0, mu0).
+hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s);
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
-                                double alpha, double mu0, double d0, int bf16, hipStream_t s);
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16, hipStream_t s);
+                                double alpha, BatchCoef cf, int bf16, hipStream_t s);
+// One layer over the first `active_tiles` tiles of the grouped grid (the matrices whose model
+// has more than q.layer layers come first).
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, hipStream_t s);
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
                                const Params* P, int entropy, int32_t* status, hipStream_t s);
 

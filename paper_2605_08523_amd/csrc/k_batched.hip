@@ -29,10 +29,11 @@ __device__ inline double wmax(double v) {
 // One workgroup per matrix: Gershgorin bounds (one wave per row) and the rescale parameters of
 // Sec. IV.1, as in the single-matrix prologue.
 __global__ void __launch_bounds__(256)
-k_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P) {
+k_batch_bounds(const BatchMat* mats, int count, Params* P) {
     const int b = blockIdx.x;
     if (b >= count) return;
     const BatchMat m = mats[b];
+    const double beta0 = m.beta0, mu0 = m.mu0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double lo = INFINITY, hi = -INFINITY;
     int bad = 0;
@@ -113,10 +114,12 @@ k_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params
 // Rescale and split of every matrix: blockIdx.y selects the matrix, blockIdx.x a chunk.
 template <bool BF>
 __global__ void __launch_bounds__(256)
-k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, double mu0, float d0) {
+k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, BatchCoef cf) {
     const int b = blockIdx.y;
     if (b >= count) return;
     const BatchMat m = mats[b];
+    const double mu0 = m.mu0;
+    const float d0 = cf.d0[m.model];
     const double scale = P[b].scale, shift = P[b].shift;
     const int64_t total = m.np * m.np;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -152,6 +155,9 @@ k_batch_layer(BatchLayerArgs q) {
         else hi = mid - 1;
     }
     const BatchMat& m = q.mats[lo];
+    const int L = q.cf.L[m.model];
+    if (q.layer >= L) return;   // not launched for such matrices; whole workgroup leaves
+    const float* cf = q.cf.coef + ((size_t)m.model * q.cf.max_L + q.layer) * 8;
     const int t = g - m.tile0;
     const int T = (int)(m.np / CfgB::BM);
     int I, J;
@@ -165,12 +171,12 @@ k_batch_layer(BatchLayerArgs q) {
     p.lo_out = m.lo[q.parity ^ 1];
     p.X = m.X;
     p.A = m.A;
-    p.a = q.a;
-    p.b = q.b;
-    p.c = q.c;
-    p.d_old = q.d_old;
-    p.d_new = q.d_new;
-    p.last = q.last;
+    p.a = cf[0];
+    p.b = cf[1];
+    p.c = cf[2];
+    p.d_old = cf[3];
+    p.d_new = cf[4];
+    p.last = q.layer == L - 1;
     p.entropy = q.entropy;
     p.D = m.D;
     p.ldd = m.ldd;
@@ -219,26 +225,25 @@ k_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials, co
 
 }  // namespace
 
-hipError_t launch_batch_bounds(const BatchMat* mats, int count, double beta0, double mu0, Params* P,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_bounds, dim3(count), dim3(256), 0, s, mats, count, beta0, mu0, P);
+hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_bounds, dim3(count), dim3(256), 0, s, mats, count, P);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
-                                double alpha, double mu0, double d0, int bf16, hipStream_t s) {
+                                double alpha, BatchCoef cf, int bf16, hipStream_t s) {
     int chunks = (int)((max_np * max_np + 4095) / 4096);
     if (chunks < 1) chunks = 1;
     if (chunks > 64) chunks = 64;
     dim3 grid(chunks, count);
     if (bf16)
-        hipLaunchKernelGGL(k_batch_rescale<true>, grid, dim3(256), 0, s, mats, count, P, alpha, mu0, (float)d0);
+        hipLaunchKernelGGL(k_batch_rescale<true>, grid, dim3(256), 0, s, mats, count, P, alpha, cf);
     else
-        hipLaunchKernelGGL(k_batch_rescale<false>, grid, dim3(256), 0, s, mats, count, P, alpha, mu0, (float)d0);
+        hipLaunchKernelGGL(k_batch_rescale<false>, grid, dim3(256), 0, s, mats, count, P, alpha, cf);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16, hipStream_t s) {
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, hipStream_t s) {
     static bool done[2] = {false, false};
     auto kern = bf16 ? k_batch_layer<true> : k_batch_layer<false>;
     if (!done[bf16]) {
@@ -248,7 +253,7 @@ hipError_t launch_batch_layer(const BatchLayerArgs& q, int total_tiles, int bf16
         if (e != hipSuccess) return e;
         done[bf16] = true;
     }
-    hipLaunchKernelGGL(kern, dim3(total_tiles), dim3(CfgB::NT), CfgB::LDS_BYTES, s, q);
+    hipLaunchKernelGGL(kern, dim3(active_tiles), dim3(CfgB::NT), CfgB::LDS_BYTES, s, q);
     return hipGetLastError();
 }
 

@@ -103,3 +103,55 @@ def test_batch_config_family(api):
         fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - Drec) / n
         print(f"[batch family {b}] N={n} clamped={info['clamped']} |dD|_F/N={fro:.3e}", flush=True)
         assert fro <= 1e-5
+
+
+BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
+        "mlsp2_L40_b1e4_mu1third"]
+
+
+def expected_choice(H, mu, kT, bank):
+    """The selection rule written out: fewest layers whose region of validity holds (beta', mu')."""
+    lo, hi = F.gershgorin(H)
+    width = hi - lo
+    mu_p = (hi - mu) / width
+    mu_p = 1.0 - mu_p if mu_p > 0.5 else mu_p
+    beta_p = width / kT
+    fits = [k for k, m in enumerate(bank)
+            if beta_p <= min(m.mu0 / mu_p, (1 - m.mu0) / (1 - mu_p)) * m.beta0]
+    return min(fits, key=lambda k: (bank[k].L, -bank[k].beta0))
+
+
+def test_model_bank_batch(api, monkeypatch):
+    from paper_2605_08523_amd import models
+    bank = [models.load(x) for x in BANK]
+    rng = np.random.default_rng(77)
+    mats = []
+    for b in range(10):
+        n = int(rng.integers(64, 400))
+        H = W.banded_decay(n, 8.0, 2.0, 900 + b)
+        lam = np.linalg.eigvalsh(H)
+        mu = float(lam[0] + rng.uniform(0.3, 0.7) * (lam[-1] - lam[0]))
+        kT = float([0.3, 0.12, 0.05, 0.02, 0.01][b % 5])
+        mats.append(dict(Hn=H, H=torch.from_numpy(H).cuda(), mu=mu, kT=kT))
+    print("case model-bank batch10 fp16x2", flush=True)
+    plan = api.BatchPlan(mats, bank, prec="fp16x2", with_entropy=True, alpha=0.842704)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert plan.status.cpu().numpy().tolist() == [0] * 10
+    want = [expected_choice(it["Hn"], it["mu"], it["kT"], bank) for it in mats]
+    print("[bank] chosen", plan.chosen.tolist(), "expected", want, flush=True)
+    assert plan.chosen.tolist() == want
+    assert len(set(want)) >= 3          # the batch really mixes models
+    monkeypatch.setenv("FE_SCHEDULE", "dp")
+    for b, it in enumerate(mats):
+        m = bank[int(plan.chosen[b])]
+        D1, tr1, _, _ = api.expand_density(it["H"], it["mu"], it["kT"], m, prec="fp16x2")
+        S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec="fp16x2")
+        torch.cuda.synchronize()
+        assert torch.equal(plan.D[b], D1), f"item {b}"
+        assert float(plan.S[b]) == float(S1)
+        ref = F.density(it["Hn"], it["mu"], it["kT"])
+        n = it["Hn"].shape[0]
+        fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - ref["D"]) / n
+        print(f"[bank item {b}] N={n} kT={it['kT']} model {m.name} |dD|_F/N={fro:.3e}", flush=True)
+        assert fro <= 1e-5
