@@ -4,7 +4,10 @@ A step is one full fe_expand_density call on a resident Hamiltonian: Gershgorin 
 all L layers (split-precision MFMA products with the fused epilogue) and the FP64 traces.
 
 Workload: 16^3 periodic Anderson lattice (N = 4096), hopping -1, on-site disorder U[-1, 1],
-kT = 0.05, mu = 0, the paper's 26-layer (beta0 = 1500, mu0 = 1/3) coefficients.
+kT = 0.05, mu = 0. The step selects the model from the bank of trained coefficient sets (fewest
+layers whose region of validity holds the matrix's beta' and mu', Sec. on the region of validity
+by layer count; for this lattice beta' = 280 selects the 22-layer beta0 = 600 model) and then
+expands; the paper's 26-layer (beta0 = 1500, mu0 = 1/3) model is timed beside it.
 
 Prints one JSON line with the throughput, the roofline of the layer kernel (timed live with HIP
 events on the launch stream), the error against the CPU FP64 eigendecomposition oracle, the
@@ -26,6 +29,8 @@ METRIC = ("density matrices/s and TFLOP/s vs FP64 recursion & eigensolver at "
           "‖ΔD‖_F/N≤1e-5")
 PEAK_TFLOPS = {"fp16x2": 2500.0, "bf16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}
 HBM_GBS = 8000.0
+BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
+        "mlsp2_L40_b1e4_mu1third"]
 
 
 def parse():
@@ -42,6 +47,8 @@ def parse():
                    help="anderson4096: the headline line (default); batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
                         "density and entropy")
+    p.add_argument("--model", default="bank",
+                   help="anderson4096: 'bank' (select per matrix, default) or one model name")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only a plain 1 GiB device-to-device copy, three times (the reference for "
                         "scaling the HBM byte counters)")
@@ -112,7 +119,6 @@ def main():
         return bench_large(args, torch, api, models, workloads, dev)
     if args.workload == "filling4096":
         return bench_filling(args, torch, api, models, workloads, dev)
-    m = models.load("mlsp2_L26_b1500_mu1third")
     c = workloads.config_anderson_4096()
     H = c["H"]
     n = H.shape[0]
@@ -120,11 +126,25 @@ def main():
     mu, kT = c["mu"], c["kT"]
     ws = api.Workspace(n)
     D = torch.empty((n, n), dtype=torch.float32, device=dev)
+    if args.model == "bank":
+        bank = [models.load(x) for x in BANK]
+        bank_refs = [api.make_model(x.theta, x.beta0, x.mu0) for x in bank]
+        m = bank[api.select_model(Hd, mu, kT, bank_refs, ws=ws)]
+    else:
+        bank = None
+        m = models.load(args.model)
     mref = api.make_model(m.theta, m.beta0, m.mu0)
     m1 = api.make_model(m.theta[-1:], m.beta0, m.mu0)      # one layer: prologue + one layer
 
-    def step():
+    def expand():
         api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws)
+
+    def step():
+        if bank is not None:
+            k = api.select_model(Hd, mu, kT, bank_refs, ws=ws)
+            api.expand_density(Hd, mu, kT, bank_refs[k], prec=args.prec, out=D, ws=ws)
+        else:
+            expand()
 
     def step1():
         api.expand_density(Hd, mu, kT, m1, prec=args.prec, out=D, ws=ws)
@@ -140,9 +160,10 @@ def main():
         return
 
     ms = timed(step, args.steps, args.warmup, torch)
+    ms_expand = timed(expand, args.steps, args.warmup, torch) if bank is not None else ms
     ms1 = timed(step1, args.steps, args.warmup, torch)
     L = m.L
-    layer_ms = (ms - ms1) / (L - 1)
+    layer_ms = (ms_expand - ms1) / (L - 1)
     flop_layer = 2.0 * n ** 3                         # algorithmic X^2 of one layer
     tile = 128 if n <= 8192 else 256
     T = -(-n // tile)
@@ -166,7 +187,10 @@ def main():
         "precision": f"{args.prec}: 16-bit hi/lo split, 3 MFMA products, fp32 accumulate; fp64 bounds, rescale and traces",
         "data": "synthetic",
         "config": {"workload": "anderson_cubic_16x16x16_periodic_N4096_t-1_W1_kT0.05_mu0",
-                   "N": n, "layers": L, "coefficients": m.name, "seed": c["seed"]},
+                   "N": n, "layers": L, "coefficients": m.name, "seed": c["seed"],
+                   "model_selection": ("fewest layers valid for (beta', mu') among " + ", ".join(BANK)
+                                       + "; selection (bounds pass + read-back) inside the step")
+                   if bank is not None else "fixed"},
         "tflops_algorithmic": L * flop_layer / (ms * 1e-3) / 1e12,
         "roofline": {
             "kernel": "k_layer_split (one layer: split MFMA X^2 + fused epilogue)",
@@ -180,10 +204,18 @@ def main():
             "layer_ms": layer_ms,
             "executed_mfma_tflops": exec_flop_layer / (layer_ms * 1e-3) / 1e12,
             "executed_frac": exec_flop_layer / (layer_ms * 1e-3) / 1e12 / peak,
-            "method": "HIP events on the launch stream: (t(L=26) - t(L=1)) / 25",
+            "method": f"HIP events on the launch stream: (t(L={L}) - t(L=1)) / {L - 1}",
         },
         "prologue_plus_one_layer_ms": ms1,
     }
+    if bank is not None:
+        out["expand_only_ms"] = ms_expand
+        m26 = models.load("mlsp2_L26_b1500_mu1third")
+        r26 = api.make_model(m26.theta, m26.beta0, m26.mu0)
+        ms26 = timed(lambda: api.expand_density(Hd, mu, kT, r26, prec=args.prec, out=D, ws=ws),
+                     args.steps, args.warmup, torch)
+        out["fixed_model_L26"] = {"coefficients": m26.name, "ms_per_step": ms26,
+                                  "value": 1000.0 / ms26}
     # the timed runs end with the one-layer model: recompute D with the full model for the error
     _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws,
                                             want_info=True)
@@ -275,8 +307,7 @@ def bench_batch(args, torch, api, models, workloads, dev):
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "status_nonzero": int(np.count_nonzero(status))}
     # the same batch over the model bank: each matrix runs the fewest layers valid for it
-    bank_names = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third",
-                  "mlsp2_L26_b1500_mu1third", "mlsp2_L40_b1e4_mu1third"]
+    bank_names = BANK
     bank = [models.load(x) for x in bank_names]
     plan.close()
     bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)

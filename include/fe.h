@@ -112,6 +112,15 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
                       double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
                       void* stream);
 
+/* Model-bank selection for one matrix: the bank model with the fewest layers whose region of
+ * validity (Eq. conditions) holds the (beta', mu') of H at (mu, kT) (ties: the larger beta0); if
+ * none does, the one with the widest region (an expansion with it clamps beta' and warns).
+ * bank: host array of nbank models. index: host, receives the chosen position. Runs the
+ * Gershgorin pass on the device and synchronizes the stream. */
+int fe_model_select(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                    const fe_model* bank, int32_t nbank, int32_t* index, fe_workspace* ws,
+                    void* stream);
+
 /* Density matrix at a prescribed occupation (Sec. IV.3): the chemical potential solving
  * Tr D(mu) = n_occ is found by Newton iterations with d Tr D / d mu = beta (Tr D - sum D_ij^2)
  * (Eq. drho traced), each iterate one full expansion as in fe_expand_density; steps that leave

@@ -67,6 +67,8 @@ SIGNATURES = {
                                          _I32, _P, _I32, _I64, _P, _P, C.POINTER(_D),
                                          C.POINTER(_I32), C.POINTER(fe_rescale_info), _P, _P]),
     "fe_observable": (_I32, [_P, _I32, _I64, _P, _I64, _I64, _P, _P, _P]),
+    "fe_model_select": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, C.POINTER(_I32),
+                               _P, _P]),
     "fe_free_energy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), C.POINTER(fe_model), _D,
                               _I32, _P, _I32, _I64, _P, _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
     "fe_expand_entropy": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _D, _I32, _P,
@@ -258,6 +260,19 @@ def expand_density_filling(H, n_occ: float, kT: float, model, prec: str = "fp16x
         C.c_void_p(tr.data_ptr()), C.c_void_p(tr.data_ptr() + 8), C.byref(mu), C.byref(iters),
         C.byref(info), ws.handle, _stream_ptr()))
     return out, mu.value, iters.value, tr[0], tr[1], info.as_dict()
+
+
+def select_model(H, mu: float, kT: float, bank, ws: Workspace | None = None) -> int:
+    """fe_model_select: index in `bank` (a list of models) of the model with the fewest layers
+    valid for H at (mu, kT). Synchronizes the stream."""
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    refs = [_model_of(x) for x in bank]
+    structs = (fe_model * len(refs))(*[r.struct for r in refs])
+    idx = C.c_int32()
+    _check(lib().fe_model_select(C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), structs,
+                                 len(refs), C.byref(idx), ws.handle, _stream_ptr()))
+    return idx.value
 
 
 def observable(D, A, ws: Workspace | None = None):

@@ -403,6 +403,30 @@ int fe_expand_density_filling(const double* H, int64_t n, int64_t ldh, double n_
     return rc;
 }
 
+int fe_model_select(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                    const fe_model* bank, int32_t nbank, int32_t* index, fe_workspace* ws,
+                    void* stream) {
+    if (!index) return fail(FE_ERR_ARG, "index is NULL");
+    if (!bank || nbank < 1) return fail(FE_ERR_ARG, "empty model bank");
+    int rc = check_common(H, n, ldh, mu, kT, ws);
+    if (rc) return rc;
+    std::vector<const fe_model*> ms;
+    for (int k = 0; k < nbank; ++k) {
+        rc = check_model(&bank[k], "bank model");
+        if (rc) return rc;
+        ms.push_back(&bank[k]);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FE_HIP(fe::launch_bounds_params(H, n, ldh, mu, kT, bank[0].beta0, bank[0].mu0, ws->bparts,
+                                    ws->params, s));
+    FE_HIP(hipStreamSynchronize(s));
+    fe::Params p;
+    FE_HIP(hipMemcpy(&p, ws->params, sizeof(p), hipMemcpyDeviceToHost));
+    if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
+    *index = choose_bank_model(ms.data(), nbank, p.emin, p.emax, mu, kT);
+    return FE_OK;
+}
+
 int fe_observable(const void* D, int32_t d_is_fp64, int64_t ldd, const double* A, int64_t lda,
                   int64_t n, double* out, fe_workspace* ws, void* stream) {
     if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");

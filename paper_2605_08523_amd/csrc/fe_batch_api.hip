@@ -334,37 +334,9 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
     FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, nullptr));
     std::vector<fe::Params> P(count);
     FE_HIP(hipMemcpy(P.data(), ws->bparams, sizeof(fe::Params) * count, hipMemcpyDeviceToHost));
-    // Smallest layer count whose region of validity (beta' <= beta_max(mu'), Eq. conditions)
-    // contains the item; if none does, the model with the largest beta_max (the item is clamped
-    // and reports FE_WARN_BETA_CLAMPED).
     std::vector<int> model(count, 0);
     for (int i = 0; i < count; ++i) {
-        const double lo = P[i].emin, hi = P[i].emax, width = hi - lo;
-        int best = -1, widest = 0;
-        double widest_b = -1.0;
-        const bool usable = isfinite(lo) && isfinite(hi) && items[i].kT > 0.0;
-        const bool degenerate = usable && !(width > 1e-300 * fmax(1.0, fabs(hi)));
-        double mu_p = 0.5, beta_p = 0.0;
-        if (usable && !degenerate) {
-            mu_p = (hi - items[i].mu) / width;
-            if (mu_p > 0.5) mu_p = 1.0 - mu_p;
-            beta_p = width / items[i].kT;
-        }
-        for (int k = 0; k < nbank; ++k) {
-            const fe_model* m = ms[k];
-            const double bmax = (mu_p > 0.0 && mu_p <= 0.5)
-                                    ? fmin(m->mu0 / mu_p, (1.0 - m->mu0) / (1.0 - mu_p)) * m->beta0
-                                    : 0.0;
-            if (bmax > widest_b) {
-                widest_b = bmax;
-                widest = k;
-            }
-            const bool fits = !usable || degenerate || beta_p <= bmax;
-            if (fits && (best < 0 || m->L < ms[best]->L ||
-                         (m->L == ms[best]->L && m->beta0 > ms[best]->beta0)))
-                best = k;
-        }
-        model[i] = best >= 0 ? best : widest;
+        model[i] = choose_bank_model(ms.data(), nbank, P[i].emin, P[i].emax, items[i].mu, items[i].kT);
         if (chosen) chosen[i] = model[i];
     }
     std::vector<const fe_model*> ent;

@@ -62,6 +62,41 @@ inline int hip_fail(hipError_t e, const char* what) {
 inline constexpr int kMaxLayers = 4096;
 inline constexpr double kDSkip = 1e-8;   // accumulator weights below this are skipped (Sec. V.A)
 
+// Model-bank rule: the bank model with the fewest layers whose region of validity (Eq.
+// conditions: beta' <= beta0 min(mu0/mu', (1 - mu0)/(1 - mu'))) holds an input with Gershgorin
+// bounds [lo, hi], chemical potential mu and temperature kT (ties: the larger beta0); if none,
+// the model with the widest region (the input is then clamped). Degenerate or unusable bounds
+// (the expansion reports those) take the fewest layers.
+inline int choose_bank_model(const fe_model* const* ms, int nbank, double lo, double hi, double mu,
+                             double kT) {
+    const double width = hi - lo;
+    const bool usable = isfinite(lo) && isfinite(hi) && kT > 0.0;
+    const bool degenerate = usable && !(width > 1e-300 * fmax(1.0, fabs(hi)));
+    double mu_p = 0.5, beta_p = 0.0;
+    if (usable && !degenerate) {
+        mu_p = (hi - mu) / width;
+        if (mu_p > 0.5) mu_p = 1.0 - mu_p;
+        beta_p = width / kT;
+    }
+    int best = -1, widest = 0;
+    double widest_b = -1.0;
+    for (int k = 0; k < nbank; ++k) {
+        const fe_model* m = ms[k];
+        const double bmax = (mu_p > 0.0 && mu_p <= 0.5)
+                                ? fmin(m->mu0 / mu_p, (1.0 - m->mu0) / (1.0 - mu_p)) * m->beta0
+                                : 0.0;
+        if (bmax > widest_b) {
+            widest_b = bmax;
+            widest = k;
+        }
+        const bool fits = !usable || degenerate || beta_p <= bmax;
+        if (fits && (best < 0 || m->L < ms[best]->L ||
+                     (m->L == ms[best]->L && m->beta0 > ms[best]->beta0)))
+            best = k;
+    }
+    return best >= 0 ? best : widest;
+}
+
 // Accumulator schedule of the 16-bit layer kernels. The recursion adds d_j X_j for j = 1 .. L-1
 // (d_0 X_0 is formed by the rescale; X_L is the output). Layer i's epilogue sees X_i (its input)
 // and X_{i+1} (its output), so each term can be added by one of two layers; terms are paired,

@@ -145,6 +145,7 @@ def test_model_bank_batch(api, monkeypatch):
     monkeypatch.setenv("FE_SCHEDULE", "dp")
     for b, it in enumerate(mats):
         m = bank[int(plan.chosen[b])]
+        assert api.select_model(it["H"], it["mu"], it["kT"], bank) == want[b], f"item {b}"
         D1, tr1, _, _ = api.expand_density(it["H"], it["mu"], it["kT"], m, prec="fp16x2")
         S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec="fp16x2")
         torch.cuda.synchronize()
