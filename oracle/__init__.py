@@ -17,6 +17,8 @@ Two layers:
   (Eq. mlsp2, Alg. 1) and the entropy expansion (Eq. entropy expansion),
   composed as in Alg. 2. It separates model error (recursion vs definition)
   from arithmetic error (GPU vs recursion at the same coefficients).
+* ``oracle.variants`` -- Skip-SP2 and Max-SP2 (Sec. III.A), scalar and matrix forms, the
+  embeddings MLSP2 -> Skip-SP2 -> Max-SP2 (App. C) and their complex-step Jacobians.
 * ``oracle.training`` -- the scalar recursion's Jacobian with respect to the
   coefficients (forward-mode sensitivities in FP64), the targets of Sec. III.C
   and the sampling densities, used to check the GPU trainer's kernels.
@@ -25,4 +27,4 @@ Parity status: every function here is pinned by a test in ``tests/`` against
 closed forms, values printed in the paper, brute force or finite differences,
 except where a docstring says "parity unpinned".
 """
-from . import fermi, recursion, training  # noqa: F401
+from . import fermi, recursion, training, variants  # noqa: F401
