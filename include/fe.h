@@ -274,6 +274,76 @@ int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_
                        const float* G, float* work, double* part, int32_t nblocks,
                        double* grad, void* stream);
 
+/* ---- Skip-SP2 and Max-SP2 (Sec. III.A) ------------------------------------------------- */
+
+#define FE_ARCH_MAX   1   /* Max-SP2 (Eq. maxsp2, Alg. maxsp2-1d) */
+#define FE_ARCH_SKIP  2   /* Skip-SP2 with k skips and K accumulators (Sec. III.A.3) */
+
+/* A Skip-SP2 or Max-SP2 model. x_0 is the rescaled matrix (the model coordinate: the rescale
+ * performs the SP2 flip) and every layer squares an affine combination of stored matrices.
+ * coef (host, fe_qmodel_coef_count doubles), in this order:
+ *  FE_ARCH_MAX, L layers: for i = 0 .. L-1: delta_i, theta_{i,0} .. theta_{i,i}; then
+ *    c, gamma_0 .. gamma_L.
+ *    x_{i+1} = (delta_i I + sum_{j<=i} theta_{i,j} x_j)^2,  f = c I + sum_{i=0}^{L} gamma_i x_i
+ *    (the output carries both printed forms: Eq. maxsp2's gamma_0 x_0 and Alg. maxsp2-1d's
+ *    constant).
+ *  FE_ARCH_SKIP: for i = 0 .. L-1: alpha_c_i, alpha_{i,0} .. alpha_{i,k-1}, beta_{i,1} ..
+ *    beta_{i,K}, gamma_{i,1} .. gamma_{i,K}; then a0_1 .. a0_K, omega.
+ *    x_{i+1} = (alpha_c_i I + sum_{j<k, i-j>=0} alpha_{i,j} x_{i-j} + sum_l beta_{i,l} A_{i,l})^2,
+ *    A_{i+1,l} = A_{i,l} + gamma_{i,l} x_i,  A_{0,l} = a0_l I,  f = omega x_L + sum_l A_{L,l}
+ *    ((1 + k + 2K) L + K + 1 coefficients: the paper's (1 + k + 2K) n + 2 at K = 1; the weight
+ *    omega on x_L is what App. C's embedding of MLSP2 needs). */
+typedef struct {
+    int32_t arch;        /* FE_ARCH_MAX or FE_ARCH_SKIP */
+    int32_t L;           /* layers (squarings), 1..64 */
+    int32_t k, K;        /* FE_ARCH_SKIP: skips 1..4 and accumulators 1..4 (ignored for Max) */
+    double beta0, mu0;   /* training point, as for fe_model (used by the rescale) */
+    const double* coef;  /* host coefficients, layout above */
+} fe_qmodel;
+
+/* Number of coefficients of a model of this shape in *count (host). */
+int fe_qmodel_coef_count(int32_t arch, int32_t L, int32_t k, int32_t K, int64_t* count);
+
+/* Device scratch the expansion of an n x n matrix with model m needs, in *bytes (host):
+ * Max-SP2 stores x_0 .. x_L, Skip-SP2 the k most recent x_i and K accumulators (FP32, padded
+ * to a multiple of 128), plus the 16-bit hi/lo operand. */
+int fe_variant_scratch_bytes(int64_t n, const fe_qmodel* m, int64_t* bytes);
+
+/* D ~ f_FD(H) through a Skip-SP2 or Max-SP2 model: Gershgorin bounds and rescale as for
+ * fe_expand_density (Sec. IV.1), then per layer one split-precision MFMA squaring (prec
+ * FE_PREC_FP16X2 or FE_PREC_BF16X2, FP32 accumulation, upper tiles) and one pass that forms the
+ * next operand from the stored states; the last pass forms f (I - f if the spectrum was
+ * flipped), writes D (float32 or, d_is_fp64, float64 values of the FP32 result; may be NULL)
+ * and reduces Tr D and sum_ij D_ij^2 in FP64 (trD, trD2: device doubles, may be NULL).
+ * scratch: device, at least fe_variant_scratch_bytes; the workspace provides the bounds and
+ * trace buffers. Asynchronous unless info is non-NULL (then as fe_expand_density).
+ * FE_ERR_RANGE if an operand leaves [-16, 16] on the model coordinate's unit interval. */
+int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                              const fe_qmodel* m, int32_t prec, void* scratch, int64_t scratch_bytes,
+                              void* D, int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                              fe_rescale_info* info, fe_workspace* ws, void* stream);
+
+/* Embedding of an MLSP2 model (Eq. mlsp2) in Skip-SP2 with k = K = 1 (arch FE_ARCH_SKIP) or in
+ * Max-SP2 (FE_ARCH_MAX), App. C: with x~_0 = x_0 and x~_{i+1} = (x_i + b_i/(2a_i))^2 the MLSP2
+ * state is x_i = a_{i-1} x~_i + c_{i-1} - b_{i-1}^2/(4a_{i-1}); the same function with the
+ * same layer count. coef_out (host) receives fe_qmodel_coef_count(arch, src->L, 1, 1) doubles.
+ * FE_ERR_ARG if some a_i is 0 (such a layer is not a square of an affine form). */
+int fe_embed_mlsp2(const fe_model* src, int32_t arch, double* coef_out);
+
+/* The scalar model at n device points y: r = f(y) - tgt (tgt may be NULL) and, if JT is not
+ * NULL, JT[p][k] = d f(y_k) / d coef_p (reverse mode, FP64). m gives the shape; its coef field
+ * is ignored: coef is a device array in the same layout. Asynchronous. */
+int fe_variant_eval(const double* y, int32_t n, const fe_qmodel* m, const double* coef,
+                    const double* tgt, double* r, double* JT, void* stream);
+
+/* Fit a Skip-SP2 or Max-SP2 model to the Fermi target of spec (spec->target must be
+ * FE_TARGET_FERMI; spec->L is ignored) by the same Levenberg-Marquardt iteration as
+ * fe_train_coeffs, starting from init (shape and host coefficients; the embedding of a trained
+ * MLSP2 model, fe_embed_mlsp2, is the intended start, App. C). coef_out (host) receives the
+ * best coefficients. Synchronizes; allocates its own device scratch for the call. */
+int fe_train_variant(const fe_train_spec* spec, const fe_qmodel* init, double* coef_out,
+                     fe_train_report* rep, void* stream);
+
 /* ---- helpers ---------------------------------------------------------------------------- */
 
 /* SP2 for a known chemical potential embedded in the layer form (Eq. sp2-mu; App. C):

@@ -40,6 +40,11 @@ class fe_model(C.Structure):
                 ("theta", C.POINTER(C.c_double))]
 
 
+class fe_qmodel(C.Structure):
+    _fields_ = [("arch", C.c_int32), ("L", C.c_int32), ("k", C.c_int32), ("K", C.c_int32),
+                ("beta0", C.c_double), ("mu0", C.c_double), ("coef", C.POINTER(C.c_double))]
+
+
 class fe_rescale_info(C.Structure):
     _fields_ = [("emin", C.c_double), ("emax", C.c_double), ("mu_p", C.c_double),
                 ("beta_p", C.c_double), ("beta_max", C.c_double), ("scale", C.c_double),
@@ -79,6 +84,14 @@ SIGNATURES = {
     "fe_matrix_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
     "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
+    "fe_qmodel_coef_count": (_I32, [_I32, _I32, _I32, _I32, C.POINTER(_I64)]),
+    "fe_variant_scratch_bytes": (_I32, [_I64, C.POINTER(fe_qmodel), C.POINTER(_I64)]),
+    "fe_expand_density_variant": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_qmodel), _I32, _P,
+                                         _I64, _P, _I32, _I64, _P, _P, C.POINTER(fe_rescale_info),
+                                         _P, _P]),
+    "fe_embed_mlsp2": (_I32, [C.POINTER(fe_model), _I32, C.POINTER(_D)]),
+    "fe_variant_eval": (_I32, [_P, _I32, C.POINTER(fe_qmodel), _P, _P, _P, _P, _P]),
+    "fe_train_variant": (_I32, [_P, C.POINTER(fe_qmodel), C.POINTER(_D), _P, _P]),
     "fe_last_error": (C.c_char_p, []),
     "fe_version": (C.c_char_p, []),
 }

@@ -19,17 +19,6 @@ using namespace fehost;
 
 namespace {
 
-int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, fe_workspace* ws) {
-    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
-    if (!H) return fail(FE_ERR_ARG, "H is NULL");
-    if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
-    if (ldh < n) return fail(FE_ERR_ARG, "ldh < n");
-    if (!(kT > 0.0) || !isfinite(kT)) return fail(FE_ERR_DOMAIN, "kT must be positive and finite");
-    if (!isfinite(mu)) return fail(FE_ERR_DOMAIN, "mu must be finite");
-    if (n > ws->max_n) return fail(FE_ERR_WORKSPACE, "n exceeds the workspace's max_n");
-    return FE_OK;
-}
-
 constexpr int64_t kStreamKMinN = 1536;   // workspaces for n >= this carry stream-K buffers
 
 // Schedule of the split-precision layer kernel (FE_SCHEDULE=dp|sk|sk2 overrides):
@@ -50,34 +39,6 @@ int use_streamk(int64_t n, const fe_workspace* ws) {
     const int64_t rounds = ntiles / grid;
     const int64_t nsk = rounds >= 2 ? ntiles - (rounds - 1) * grid : ntiles;
     return nsk * nk >= 8 * grid ? 2 : 0;
-}
-
-int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
-    FE_HIP(hipStreamSynchronize(s));
-    fe::Params p;
-    FE_HIP(hipMemcpy(&p, ws->params + which, sizeof(p), hipMemcpyDeviceToHost));
-    if (ws->sk_err) {
-        int err = 0;
-        FE_HIP(hipMemcpy(&err, ws->sk_err, sizeof(int), hipMemcpyDeviceToHost));
-        if (err) {
-            FE_HIP(hipMemset(ws->sk_err, 0, sizeof(int)));
-            return fail(FE_ERR_HIP, "a stream-K workgroup gave up waiting for a partial tile");
-        }
-    }
-    info->emin = p.emin;
-    info->emax = p.emax;
-    info->mu_p = p.mu_p;
-    info->beta_p = p.beta_p;
-    info->beta_max = p.beta_max;
-    info->scale = p.scale;
-    info->shift = p.shift;
-    info->flipped = p.flipped;
-    info->clamped = p.clamped;
-    info->degenerate = p.degenerate;
-    info->status = p.status;
-    if (p.status == FE_ERR_DOMAIN) return fail(FE_ERR_DOMAIN, "mu lies outside the Gershgorin bounds of H");
-    if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
-    return p.status;
 }
 
 // Slot carving for the precision modes (np x np elements each).

@@ -97,6 +97,104 @@ inline int choose_bank_model(const fe_model* const* ms, int nbank, double lo, do
     return best >= 0 ? best : widest;
 }
 
+// Argument checks shared by the single-matrix entry points.
+inline int check_common(const double* H, int64_t n, int64_t ldh, double mu, double kT, fe_workspace* ws) {
+    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
+    if (!H) return fail(FE_ERR_ARG, "H is NULL");
+    if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
+    if (ldh < n) return fail(FE_ERR_ARG, "ldh < n");
+    if (!(kT > 0.0) || !isfinite(kT)) return fail(FE_ERR_DOMAIN, "kT must be positive and finite");
+    if (!isfinite(mu)) return fail(FE_ERR_DOMAIN, "mu must be finite");
+    if (n > ws->max_n) return fail(FE_ERR_WORKSPACE, "n exceeds the workspace's max_n");
+    return FE_OK;
+}
+
+// Waits for the stream, copies the rescale parameters of workspace slot `which` into *info and
+// returns their status (stream-K wait failures are reported as FE_ERR_HIP).
+inline int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
+    FE_HIP(hipStreamSynchronize(s));
+    fe::Params p;
+    FE_HIP(hipMemcpy(&p, ws->params + which, sizeof(p), hipMemcpyDeviceToHost));
+    if (ws->sk_err) {
+        int err = 0;
+        FE_HIP(hipMemcpy(&err, ws->sk_err, sizeof(int), hipMemcpyDeviceToHost));
+        if (err) {
+            FE_HIP(hipMemset(ws->sk_err, 0, sizeof(int)));
+            return fail(FE_ERR_HIP, "a stream-K workgroup gave up waiting for a partial tile");
+        }
+    }
+    info->emin = p.emin;
+    info->emax = p.emax;
+    info->mu_p = p.mu_p;
+    info->beta_p = p.beta_p;
+    info->beta_max = p.beta_max;
+    info->scale = p.scale;
+    info->shift = p.shift;
+    info->flipped = p.flipped;
+    info->clamped = p.clamped;
+    info->degenerate = p.degenerate;
+    info->status = p.status;
+    if (p.status == FE_ERR_DOMAIN) return fail(FE_ERR_DOMAIN, "mu lies outside the Gershgorin bounds of H");
+    if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
+    return p.status;
+}
+
+// ---- Skip-SP2 / Max-SP2 models (coefficient layout of fe_qmodel) ----
+
+inline int64_t qmodel_coef_count(int arch, int L, int k, int K) {
+    if (arch == FE_ARCH_MAX) return (int64_t)L * (L + 3) / 2 + L + 2;
+    return (int64_t)(1 + k + 2 * K) * L + K + 1;
+}
+
+inline int check_qmodel(const fe_qmodel* m) {
+    if (!m || !m->coef) return fail(FE_ERR_ARG, "model or its coefficients are NULL");
+    if (m->arch != FE_ARCH_MAX && m->arch != FE_ARCH_SKIP) return fail(FE_ERR_ARG, "unknown model family");
+    if (m->L < 1 || m->L > 64) return fail(FE_ERR_ARG, "layer count out of range (1..64)");
+    if (m->arch == FE_ARCH_SKIP && (m->k < 1 || m->k > 4 || m->K < 1 || m->K > 4))
+        return fail(FE_ERR_ARG, "Skip-SP2 needs 1 <= k <= 4 and 1 <= K <= 4");
+    if (!(m->beta0 > 0.0) || !(m->mu0 > 0.0 && m->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
+    const int64_t P = qmodel_coef_count(m->arch, m->L, m->k, m->K);
+    for (int64_t p = 0; p < P; ++p)
+        if (!isfinite(m->coef[p])) return fail(FE_ERR_ARG, "non-finite coefficient");
+    return FE_OK;
+}
+
+// Scalar model value at y in FP64; *zmax (if not null) receives the largest |operand| met.
+inline double qmodel_value(int arch, int L, int k, int K, const double* c, double y, double* zmax) {
+    std::vector<double> x(L + 1);
+    x[0] = y;
+    double zm = 0.0, f;
+    if (arch == FE_ARCH_MAX) {
+        int off = 0;
+        for (int i = 0; i < L; ++i) {
+            double z = c[off];
+            for (int j = 0; j <= i; ++j) z += c[off + 1 + j] * x[j];
+            zm = fmax(zm, fabs(z));
+            x[i + 1] = z * z;
+            off += i + 2;
+        }
+        f = c[off];
+        for (int j = 0; j <= L; ++j) f += c[off + 1 + j] * x[j];
+    } else {
+        const int per = 1 + k + 2 * K;
+        std::vector<double> A(c + (size_t)per * L, c + (size_t)per * L + K);
+        for (int i = 0; i < L; ++i) {
+            const double* ci = c + (size_t)per * i;
+            double z = ci[0];
+            for (int j = 0; j < k; ++j)
+                if (i - j >= 0) z += ci[1 + j] * x[i - j];
+            for (int l = 0; l < K; ++l) z += ci[1 + k + l] * A[l];
+            for (int l = 0; l < K; ++l) A[l] += ci[1 + k + K + l] * x[i];
+            zm = fmax(zm, fabs(z));
+            x[i + 1] = z * z;
+        }
+        f = c[(size_t)per * L + K] * x[L];
+        for (int l = 0; l < K; ++l) f += A[l];
+    }
+    if (zmax) *zmax = zm;
+    return f;
+}
+
 // Accumulator schedule of the 16-bit layer kernels. The recursion adds d_j X_j for j = 1 .. L-1
 // (d_0 X_0 is formed by the rescale; X_L is the output). Layer i's epilogue sees X_i (its input)
 // and X_{i+1} (its output), so each term can be added by one of two layers; terms are paired,

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fe_host.h"
+#include "fe_variant.h"
 
 using namespace fehost;
 
@@ -118,85 +119,23 @@ double model_value(const double* th, int L, int target, double mu0, double alpha
 
 struct DevBufs {
     double *y = nullptr, *tgt = nullptr, *r = nullptr, *JT = nullptr, *G = nullptr, *g = nullptr, *v = nullptr;
+    double* coef = nullptr;
     void release() {
-        for (double* p : {y, tgt, r, JT, G, g, v})
+        for (double* p : {y, tgt, r, JT, G, g, v, coef})
             if (p) (void)hipFree(p);
     }
 };
 
-}  // namespace
-
-extern "C" {
-
-int fe_scalar_eval(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
-                   double mu0, double alpha, const double* tgt, double* r, double* JT, void* stream) {
-    if (!y || !r || !theta || n < 1) return fail(FE_ERR_ARG, "bad arguments");
-    if (L < 1 || L > fe::scalar_max_layers()) return fail(FE_ERR_ARG, "L out of range for the scalar kernel");
-    if (target != FE_TARGET_FERMI && target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
-    fe::ScalarArgs a{};
-    a.y = y; a.tgt = tgt; a.r = r; a.JT = JT; a.n = n; a.L = L; a.target = target;
-    a.mu0 = mu0; a.alpha = alpha;
-    memcpy(a.theta, theta, sizeof(double) * 4 * L);
-    FE_HIP(fe::launch_scalar_eval(a, static_cast<hipStream_t>(stream)));
-    return FE_OK;
-}
-
-int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double* theta_out,
-                    fe_train_report* rep, fe_workspace* ws, void* stream) {
-    (void)ws;
-    if (!spec || !theta_out) return fail(FE_ERR_ARG, "spec and theta_out are required");
-    const int L = spec->L, n = spec->n_points, P = 4 * L;
-    if (L < 1 || L > fe::scalar_max_layers()) return fail(FE_ERR_ARG, "L out of range");
-    if (n < P) return fail(FE_ERR_ARG, "need at least 4L sample points");
-    if (!(spec->beta0 > 0.0) || !(spec->mu0 > 0.0 && spec->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
-    if (spec->target != FE_TARGET_FERMI && spec->target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const double b0 = spec->beta0, m0 = spec->mu0;
-    const double alpha = spec->target == FE_TARGET_ENTROPY ? spec->alpha : 1.0;
-
-    std::vector<double> th(P);
-    if (theta_init) {
-        memcpy(th.data(), theta_init, sizeof(double) * P);
-    } else {
-        // SP2 embedding (Eq. sp2-mu, App. C) for as many layers as the slope needs
-        // (Eq. layer count), identity layers after it
-        const int nl = std::max(1, std::min(L, (int)lround(fe_layer_count(b0))));
-        std::vector<double> sp(4 * nl);
-        fe_sp2_coeffs(m0, nl, sp.data());
-        for (int i = 0; i < L; ++i) {
-            double* t = th.data() + 4 * i;
-            if (i < nl) memcpy(t, sp.data() + 4 * i, sizeof(double) * 4);
-            else { t[0] = 0.0; t[1] = 1.0; t[2] = 0.0; t[3] = 0.0; }
-        }
-    }
-    std::vector<double> y = sample_points(n, b0, m0, spec->sampling);
-    std::vector<double> tg(n);
-    for (int k = 0; k < n; ++k)
-        tg[k] = spec->target == FE_TARGET_ENTROPY ? entropy_target(y[k], b0, m0) : fermi_target(y[k], b0, m0);
-
-    // Training scratch lives for this call only (the trainer is not on the expansion's path).
-    DevBufs d;
-    hipError_t e = hipSuccess;
-    for (double** p : {&d.y, &d.tgt, &d.r, &d.v})
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.JT), sizeof(double) * (size_t)P * n);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.G), sizeof(double) * (size_t)P * P);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.g), sizeof(double) * P);
-    if (e == hipSuccess) e = hipMemcpy(d.y, y.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d.tgt, tg.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        d.release();
-        return hip_fail(e, "trainer scratch");
-    }
-
-    fe::ScalarArgs sa{};
-    sa.y = d.y; sa.tgt = d.tgt; sa.n = n; sa.L = L; sa.target = spec->target; sa.mu0 = m0; sa.alpha = alpha;
-    std::vector<double> r(n), rp(n), rm(n), G((size_t)P * P), g(P), Gl((size_t)P * P), dmax(P, 0.0);
+// Levenberg-Marquardt with geodesic acceleration over P coefficients and n residuals (see the
+// file comment). launch(th, jac) enqueues the residuals at th into d.r and, if jac, the Jacobian
+// transposed into d.JT, on stream s. On return th holds the best coefficients, r their
+// residuals (host), and it / lam the iterations and final damping.
+template <class Launch>
+hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r, DevBufs& d,
+                  hipStream_t s, int max_iter, double tol, Launch launch, int& it, double& lam) {
+    std::vector<double> rp(n), rm(n), G((size_t)P * P), g(P), Gl((size_t)P * P), dmax(P, 0.0);
     auto eval = [&](const std::vector<double>& t, std::vector<double>& out, bool jac) -> hipError_t {
-        memcpy(sa.theta, t.data(), sizeof(double) * P);
-        sa.r = d.r;
-        sa.JT = jac ? d.JT : nullptr;
-        hipError_t err = fe::launch_scalar_eval(sa, s);
+        hipError_t err = launch(t, jac);
         if (err == hipSuccess) err = hipMemcpyAsync(out.data(), d.r, sizeof(double) * n, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         return err;
@@ -221,14 +160,14 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
         return m;
     };
 
-    double lam = 1e-3;
-    int it = 0, rc = FE_OK;
-    e = eval(th, r, true);
+    lam = 1e-3;
+    it = 0;
+    hipError_t e = eval(th, r, true);
     double C = cost(r);
     bool have_gram = false;
     std::vector<double> dl(P), acc(P), tn(P), tmp(P);
-    for (; e == hipSuccess && it < spec->max_iter; ++it) {
-        if (maxabs(r) < spec->tol) break;
+    for (; e == hipSuccess && it < max_iter; ++it) {
+        if (maxabs(r) < tol) break;
         if (!have_gram) {
             e = gram(true, nullptr, g);
             if (e != hipSuccess) break;
@@ -289,13 +228,103 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
             e = eval(th, r, true);   // restore J at the current point
         }
     }
+    return e;
+}
+
+// Device scratch of one fit: n points, P coefficients (with an optional coefficient buffer).
+hipError_t alloc_fit(DevBufs& d, int n, int P, const std::vector<double>& y, const std::vector<double>& tg) {
+    hipError_t e = hipSuccess;
+    for (double** p : {&d.y, &d.tgt, &d.r, &d.v})
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.JT), sizeof(double) * (size_t)P * n);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.G), sizeof(double) * (size_t)P * P);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.g), sizeof(double) * P);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.coef), sizeof(double) * P);
+    if (e == hipSuccess) e = hipMemcpy(d.y, y.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.tgt, tg.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fe_scalar_eval(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
+                   double mu0, double alpha, const double* tgt, double* r, double* JT, void* stream) {
+    if (!y || !r || !theta || n < 1) return fail(FE_ERR_ARG, "bad arguments");
+    if (L < 1 || L > fe::scalar_max_layers()) return fail(FE_ERR_ARG, "L out of range for the scalar kernel");
+    if (target != FE_TARGET_FERMI && target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
+    fe::ScalarArgs a{};
+    a.y = y; a.tgt = tgt; a.r = r; a.JT = JT; a.n = n; a.L = L; a.target = target;
+    a.mu0 = mu0; a.alpha = alpha;
+    memcpy(a.theta, theta, sizeof(double) * 4 * L);
+    FE_HIP(fe::launch_scalar_eval(a, static_cast<hipStream_t>(stream)));
+    return FE_OK;
+}
+
+int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double* theta_out,
+                    fe_train_report* rep, fe_workspace* ws, void* stream) {
+    (void)ws;
+    if (!spec || !theta_out) return fail(FE_ERR_ARG, "spec and theta_out are required");
+    const int L = spec->L, n = spec->n_points, P = 4 * L;
+    if (L < 1 || L > fe::scalar_max_layers()) return fail(FE_ERR_ARG, "L out of range");
+    if (n < P) return fail(FE_ERR_ARG, "need at least 4L sample points");
+    if (!(spec->beta0 > 0.0) || !(spec->mu0 > 0.0 && spec->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
+    if (spec->target != FE_TARGET_FERMI && spec->target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double b0 = spec->beta0, m0 = spec->mu0;
+    const double alpha = spec->target == FE_TARGET_ENTROPY ? spec->alpha : 1.0;
+
+    std::vector<double> th(P);
+    if (theta_init) {
+        memcpy(th.data(), theta_init, sizeof(double) * P);
+    } else {
+        // SP2 embedding (Eq. sp2-mu, App. C) for as many layers as the slope needs
+        // (Eq. layer count), identity layers after it
+        const int nl = std::max(1, std::min(L, (int)lround(fe_layer_count(b0))));
+        std::vector<double> sp(4 * nl);
+        fe_sp2_coeffs(m0, nl, sp.data());
+        for (int i = 0; i < L; ++i) {
+            double* t = th.data() + 4 * i;
+            if (i < nl) memcpy(t, sp.data() + 4 * i, sizeof(double) * 4);
+            else { t[0] = 0.0; t[1] = 1.0; t[2] = 0.0; t[3] = 0.0; }
+        }
+    }
+    std::vector<double> y = sample_points(n, b0, m0, spec->sampling);
+    std::vector<double> tg(n);
+    for (int k = 0; k < n; ++k)
+        tg[k] = spec->target == FE_TARGET_ENTROPY ? entropy_target(y[k], b0, m0) : fermi_target(y[k], b0, m0);
+
+    // Training scratch lives for this call only (the trainer is not on the expansion's path).
+    DevBufs d;
+    hipError_t e = alloc_fit(d, n, P, y, tg);
+    if (e != hipSuccess) {
+        d.release();
+        return hip_fail(e, "trainer scratch");
+    }
+    fe::ScalarArgs sa{};
+    sa.y = d.y; sa.tgt = d.tgt; sa.n = n; sa.L = L; sa.target = spec->target; sa.mu0 = m0; sa.alpha = alpha;
+    auto launch = [&](const std::vector<double>& t, bool jac) -> hipError_t {
+        memcpy(sa.theta, t.data(), sizeof(double) * P);
+        sa.r = d.r;
+        sa.JT = jac ? d.JT : nullptr;
+        return fe::launch_scalar_eval(sa, s);
+    };
+    std::vector<double> r(n);
+    int it = 0, rc = FE_OK;
+    double lam = 0.0;
+    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, it, lam);
     d.release();
     if (e != hipSuccess) return hip_fail(e, "trainer");
     memcpy(theta_out, th.data(), sizeof(double) * P);
-    const double emax = maxabs(r);
+    double emax = 0.0, ss = 0.0;
+    for (double v : r) {
+        emax = std::max(emax, fabs(v));
+        ss += v * v;
+    }
     if (rep) {
         rep->iters = it;
-        rep->rms = sqrt(2.0 * C / n);
+        rep->rms = sqrt(ss / n);
         rep->max_err_points = emax;
         rep->lambda = lam;
         double gmax = 0.0;
@@ -310,6 +339,69 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
     if (emax >= spec->tol) rc = FE_ERR_NO_CONVERGENCE;
     if (rc) fail(rc, "the fit stopped above its tolerance (theta_out holds the best coefficients found)");
     return rc;
+}
+
+int fe_train_variant(const fe_train_spec* spec, const fe_qmodel* init, double* coef_out,
+                     fe_train_report* rep, void* stream) {
+    if (!spec || !coef_out) return fail(FE_ERR_ARG, "spec and coef_out are required");
+    int rc = check_qmodel(init);
+    if (rc) return rc;
+    if (spec->target != FE_TARGET_FERMI) return fail(FE_ERR_ARG, "the variant trainer fits the Fermi target");
+    if (!(spec->beta0 > 0.0) || !(spec->mu0 > 0.0 && spec->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
+    const int P = (int)qmodel_coef_count(init->arch, init->L, init->k, init->K), n = spec->n_points;
+    if (n < P) return fail(FE_ERR_ARG, "need at least as many sample points as coefficients");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double b0 = spec->beta0, m0 = spec->mu0;
+    std::vector<double> th(init->coef, init->coef + P);
+    std::vector<double> y = sample_points(n, b0, m0, spec->sampling);
+    std::vector<double> tg(n);
+    for (int k = 0; k < n; ++k) tg[k] = fermi_target(y[k], b0, m0);
+    DevBufs d;
+    hipError_t e = alloc_fit(d, n, P, y, tg);
+    if (e != hipSuccess) {
+        d.release();
+        return hip_fail(e, "trainer scratch");
+    }
+    fe::VariantEvalArgs va{};
+    va.y = d.y; va.tgt = d.tgt; va.r = d.r; va.coef = d.coef; va.n = n;
+    va.arch = init->arch; va.L = init->L; va.k = init->k; va.K = init->K;
+    auto launch = [&](const std::vector<double>& t, bool jac) -> hipError_t {
+        hipError_t err = hipMemcpyAsync(d.coef, t.data(), sizeof(double) * P, hipMemcpyHostToDevice, s);
+        va.JT = jac ? d.JT : nullptr;
+        if (err == hipSuccess) err = fe::launch_variant_eval(va, s);
+        return err;
+    };
+    std::vector<double> r(n);
+    int it = 0;
+    double lam = 0.0;
+    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, it, lam);
+    d.release();
+    if (e != hipSuccess) return hip_fail(e, "trainer");
+    memcpy(coef_out, th.data(), sizeof(double) * P);
+    double emax = 0.0, ss = 0.0;
+    for (double v : r) {
+        emax = std::max(emax, fabs(v));
+        ss += v * v;
+    }
+    if (rep) {
+        rep->iters = it;
+        rep->rms = sqrt(ss / n);
+        rep->max_err_points = emax;
+        rep->lambda = lam;
+        double gmax = 0.0;
+        const int ng = 200001;
+        for (int k = 0; k < ng; ++k) {
+            const double yy = (double)k / (ng - 1);
+            const double f = qmodel_value(init->arch, init->L, init->k, init->K, th.data(), yy, nullptr);
+            gmax = std::max(gmax, fabs(f - fermi_target(yy, b0, m0)));
+        }
+        rep->max_err_grid = gmax;
+    }
+    if (emax >= spec->tol) {
+        fail(FE_ERR_NO_CONVERGENCE, "the fit stopped above its tolerance (coef_out holds the best coefficients found)");
+        return FE_ERR_NO_CONVERGENCE;
+    }
+    return FE_OK;
 }
 
 int fe_matrix_forward(float* hist, int64_t n, const double* theta, int32_t L, float* P,
