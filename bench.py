@@ -43,7 +43,8 @@ def parse():
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
     p.add_argument("--workload", default="anderson4096",
-                   choices=["anderson4096", "batch1024", "large16384", "filling4096"],
+                   choices=["anderson4096", "batch1024", "large16384", "filling4096",
+                            "variants4096"],
                    help="anderson4096: the headline line (default); batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
                         "density and entropy")
@@ -119,6 +120,8 @@ def main():
         return bench_large(args, torch, api, models, workloads, dev)
     if args.workload == "filling4096":
         return bench_filling(args, torch, api, models, workloads, dev)
+    if args.workload == "variants4096":
+        return bench_variants(args, torch, api, models, workloads, dev)
     c = workloads.config_anderson_4096()
     H = c["H"]
     n = H.shape[0]
@@ -438,6 +441,77 @@ def bench_filling(args, torch, api, models, workloads, dev):
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "kind": "oracle",
                                "sample": "the full matrix: eigenvalues, bisection for mu, then "
                                          "eigendecomposition + assembly at that mu (FP64)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_variants(args, torch, api, models, workloads, dev):
+    """Skip-SP2 (k = K = 1) and Max-SP2 on the N = 4096 Anderson workload (Sec. III.A), each the
+    App. C embedding of the 22-layer model the bank selects for this lattice (the same function
+    as the MLSP2 path): per layer one square-only split MFMA pass and one HBM-bound combine pass.
+    Timed beside the fused MLSP2 path on the same matrix; errors against the oracle's exact D."""
+    import numpy as np
+
+    from paper_2605_08523_amd import variants
+    base = models.load("mlsp2_L22_b600_mu1third")
+    c = workloads.config_anderson_4096()
+    H = c["H"]
+    n = H.shape[0]
+    Hd = torch.from_numpy(H).to(dev)
+    mu, kT = c["mu"], c["kT"]
+    ws = api.Workspace(n)
+    D = torch.empty((n, n), dtype=torch.float32, device=dev)
+    mref = api.make_model(base.theta, base.beta0, base.mu0)
+    fams = {"max": variants.embed_mlsp2(base, "max"), "skip": variants.embed_mlsp2(base, "skip")}
+    scratch = {k: torch.empty(variants.scratch_bytes(n, q), dtype=torch.uint8, device=dev)
+               for k, q in fams.items()}
+    if args.profile:
+        for _ in range(args.warmup + args.steps):
+            for k, q in fams.items():
+                variants.expand_density_variant(Hd, mu, kT, q, prec=args.prec, out=D,
+                                                scratch=scratch[k], ws=ws)
+        torch.cuda.synchronize()
+        print("profile run done", flush=True)
+        return
+    ms_m = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws),
+                 args.steps, args.warmup, torch)
+    res = {}
+    ref = None
+    if not args.no_cpu_baseline:
+        from oracle import fermi as F
+        ref = F.density(H, mu, kT)
+    np_ = -(-n // 128) * 128
+    upper = np_ * (np_ + 64) // 2            # elements of the upper 64 x 64 tiles
+    for k, q in fams.items():
+        ms = timed(lambda: variants.expand_density_variant(Hd, mu, kT, q, prec=args.prec, out=D,
+                                                           scratch=scratch[k], ws=ws),
+                   args.steps, args.warmup, torch)
+        L = q.L
+        # combine passes, per upper element: each stored state it reads once (4 B), each
+        # accumulator it writes (4 B), hi/lo of the tile and its mirror (8 B); the result pass
+        # reads the output terms and writes D for both triangles (8 B)
+        if k == "max":
+            per_layer = [4 * (i + 1) + 8 for i in range(L)]
+            final = 4 * (L + 1) + 8
+        else:
+            per_layer = [4 * (1 + (1 if i > 0 else 0)) + 4 + 8 for i in range(L)]
+            final = 4 * 2 + 8
+        comb_bytes = upper * (sum(per_layer) + final)
+        r = {"ms_per_step": ms, "value": 1000.0 / ms, "layers": L, "coefficients": len(q.coef),
+             "combine_algorithmic_bytes_per_step": comb_bytes,
+             "slowdown_vs_fused_mlsp2": ms / ms_m}
+        if ref is not None:
+            r["error_vs_oracle_fro_over_N"] = float(np.linalg.norm(D.double().cpu().numpy() -
+                                                                   ref["D"]) / n)
+        res[k] = r
+    out = {"metric": "density matrices/s, Skip-SP2 / Max-SP2 embeddings of the selected model",
+           "value": res["skip"]["value"], "unit": "density matrices/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["skip"]["ms_per_step"],
+           "higher_is_better": True, "dtype": "f16" if args.prec == "fp16x2" else "bf16",
+           "data": "synthetic",
+           "config": {"workload": "anderson_cubic_16x16x16_periodic_N4096_t-1_W1_kT0.05_mu0",
+                      "N": n, "model": "App. C embedding of mlsp2_L22_b600_mu1third",
+                      "precision": args.prec},
+           "skip_sp2_k1_K1": res["skip"], "max_sp2": res["max"], "fused_mlsp2_ms": ms_m}
     print(json.dumps(out), flush=True)
 
 

@@ -90,11 +90,22 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
         floatx4 z;
 #pragma unroll
         for (int k = 0; k < 4; ++k) z[k] = (gr == J0 + cg + k) ? a.diag : 0.0f;
-        for (int t = 0; t < a.nterm; ++t) {
-            const floatx4 v = *reinterpret_cast<const floatx4*>(a.term[t] + gi);
-            const float w = a.w[t];
+        // terms in groups of four, the group's loads issued before its FMAs (Max-SP2 reads up
+        // to L + 1 states per element)
+        int t = 0;
+        for (; t + 4 <= a.nterm; t += 4) {
+            floatx4 v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) z[k] = fmaf(w, v[k], z[k]);
+            for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const floatx4*>(a.term[t + u] + gi);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) z[k] = fmaf(a.w[t + u], v[u][k], z[k]);
+        }
+        for (; t < a.nterm; ++t) {
+            const floatx4 v = *reinterpret_cast<const floatx4*>(a.term[t] + gi);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) z[k] = fmaf(a.w[t], v[k], z[k]);
         }
         if (a.nacc > 0) {
             const floatx4 src = *reinterpret_cast<const floatx4*>(a.acc_src + gi);
