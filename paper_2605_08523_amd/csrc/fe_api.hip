@@ -136,6 +136,11 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
         ra.X32 = b.X; ra.A32 = b.A; ra.hi = b.hi[0]; ra.lo = b.lo[0];
         ra.mode = 0; ra.bf16 = bf;
+        // squared-affine layers for FP16x2 unless FE_FORM=mlsp2 or the coefficients do not allow
+        // them; BF16x2 keeps the FP32 state (its 16-bit split would carry the state alone)
+        AffineForm af;
+        if (!bf && affine_allowed()) af = affine_form(m, alpha, dval);
+        ra.op_shift = af.ok ? af.op_shift : 0.0;
         FE_HIP(fe::launch_rescale(ra, s));
         const int T = (int)(np / tile);
         npart = T * (T + 1) / 2;
@@ -148,9 +153,16 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             la.hi_in = b.hi[i & 1]; la.lo_in = b.lo[i & 1];
             la.hi_out = b.hi[(i + 1) & 1]; la.lo_out = b.lo[(i + 1) & 1];
             la.X = b.X; la.A = b.A;
-            la.a = (float)th[4 * i]; la.b = (float)th[4 * i + 1]; la.c = (float)th[4 * i + 2];
-            la.d_old = d_old[i];
-            la.d_new = d_new[i];
+            if (af.ok) {
+                la.affine = 1;
+                la.a = af.ca[i]; la.b = 0.0f; la.c = af.cc[i];
+                la.d_old = 0.0f;
+                la.d_new = af.dnew[i];
+            } else {
+                la.a = (float)th[4 * i]; la.b = (float)th[4 * i + 1]; la.c = (float)th[4 * i + 2];
+                la.d_old = d_old[i];
+                la.d_new = d_new[i];
+            }
             la.last = (i + 1 == m->L);
             la.out_mode = out_mode; la.entropy = entropy; la.D = D; la.ldd = ldd;
             la.P = P; la.partials = tp;

@@ -40,10 +40,13 @@ struct PassTables {
     std::vector<float> coef;
     std::vector<int32_t> L;
     std::vector<float> d0;
+    std::vector<double> shift0;
     int max_L = 0;
 };
 
-PassTables make_tables(const std::vector<const fe_model*>& ms, int prec) {
+// Per model the layer weights of the single-matrix path, in the same form (squared-affine when
+// the coefficients allow it, decided with the same alpha) so both give bitwise equal results.
+PassTables make_tables(const std::vector<const fe_model*>& ms, int prec, double alpha) {
     PassTables t;
     for (const fe_model* m : ms) t.max_L = std::max(t.max_L, (int)m->L);
     t.coef.assign(ms.size() * t.max_L * 8, 0.0f);
@@ -54,18 +57,28 @@ PassTables make_tables(const std::vector<const fe_model*>& ms, int prec) {
             const double d = th[4 * i + 3];
             return (prec != FE_PREC_FP64 && fabs(d) < kDSkip) ? 0.0 : d;
         };
+        AffineForm af;
+        if (prec == FE_PREC_FP16X2 && affine_allowed()) af = affine_form(m, alpha, dval);
         std::vector<float> d_old, d_new;
         pair_accumulator_terms(m->L, dval, d_old, d_new);
         for (int l = 0; l < m->L; ++l) {
             float* c = &t.coef[(k * t.max_L + l) * 8];
-            c[0] = (float)th[4 * l];
-            c[1] = (float)th[4 * l + 1];
-            c[2] = (float)th[4 * l + 2];
-            c[3] = d_old[l];
-            c[4] = d_new[l];
+            if (af.ok) {
+                c[0] = af.ca[l];
+                c[2] = af.cc[l];
+                c[4] = af.dnew[l];
+                c[5] = 1.0f;
+            } else {
+                c[0] = (float)th[4 * l];
+                c[1] = (float)th[4 * l + 1];
+                c[2] = (float)th[4 * l + 2];
+                c[3] = d_old[l];
+                c[4] = d_new[l];
+            }
         }
         t.L.push_back(m->L);
         t.d0.push_back((float)dval(0));
+        t.shift0.push_back(af.ok ? af.op_shift : 0.0);
     }
     return t;
 }
@@ -176,9 +189,9 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
     });
     int64_t tiles = 0, max_np = 0;
     std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, &tiles, &max_np);
-    const PassTables td = make_tables(dens, prec);
+    const PassTables td = make_tables(dens, prec, 1.0);
     PassTables te;
-    if (!ent.empty()) te = make_tables(ent, prec);
+    if (!ent.empty()) te = make_tables(ent, prec, alpha);
     // active tiles per layer (the sorted order makes them a prefix in both passes)
     auto active_tiles = [&](const PassTables& t) {
         std::vector<int> act(t.max_L, 0);
@@ -204,11 +217,13 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
     fe_batch_plan* plan = new fe_batch_plan();
     plan->count = count;
     plan->ws = ws;
-    // device tables: [density coef | density L | density d0 | entropy ...], 256-byte aligned parts
+    // device tables: [density coef | L | d0 | shift0 | entropy ...], 256-byte aligned parts
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t cd = al(td.coef.size() * 4), ld = al(td.L.size() * 4), dd = al(td.d0.size() * 4);
+    const size_t sd = al(td.shift0.size() * 8);
     const size_t ce = al(te.coef.size() * 4), le = al(te.L.size() * 4), de = al(te.d0.size() * 4);
-    hipError_t e = hipMalloc(&plan->tables, cd + ld + dd + ce + le + de + 256);
+    const size_t se = al(te.shift0.size() * 8);
+    hipError_t e = hipMalloc(&plan->tables, cd + ld + dd + sd + ce + le + de + se + 256);
     if (e != hipSuccess) {
         delete plan;
         return hip_fail(e, "hipMalloc (batch tables)");
@@ -218,17 +233,21 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
         return bytes ? hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
     fe::BatchCoef cfd{reinterpret_cast<const float*>(base), reinterpret_cast<const int32_t*>(base + cd),
-                      reinterpret_cast<const float*>(base + cd + ld), td.max_L};
-    const size_t eo = cd + ld + dd;
+                      reinterpret_cast<const float*>(base + cd + ld),
+                      reinterpret_cast<const double*>(base + cd + ld + dd), td.max_L};
+    const size_t eo = cd + ld + dd + sd;
     fe::BatchCoef cfe{reinterpret_cast<const float*>(base + eo),
                       reinterpret_cast<const int32_t*>(base + eo + ce),
-                      reinterpret_cast<const float*>(base + eo + ce + le), te.max_L};
+                      reinterpret_cast<const float*>(base + eo + ce + le),
+                      reinterpret_cast<const double*>(base + eo + ce + le + de), te.max_L};
     e = up(0, td.coef.data(), td.coef.size() * 4);
     if (e == hipSuccess) e = up(cd, td.L.data(), td.L.size() * 4);
     if (e == hipSuccess) e = up(cd + ld, td.d0.data(), td.d0.size() * 4);
+    if (e == hipSuccess) e = up(cd + ld + dd, td.shift0.data(), td.shift0.size() * 8);
     if (e == hipSuccess) e = up(eo, te.coef.data(), te.coef.size() * 4);
     if (e == hipSuccess) e = up(eo + ce, te.L.data(), te.L.size() * 4);
     if (e == hipSuccess) e = up(eo + ce + le, te.d0.data(), te.d0.size() * 4);
+    if (e == hipSuccess) e = up(eo + ce + le + de, te.shift0.data(), te.shift0.size() * 8);
     if (e != hipSuccess) {
         fe_batch_plan_destroy(plan);
         return hip_fail(e, "hipMemcpy (batch tables)");

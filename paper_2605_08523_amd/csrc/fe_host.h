@@ -3,6 +3,8 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <string>
 #include <vector>
@@ -192,6 +194,68 @@ inline double qmodel_value(int arch, int L, int k, int K, const double* c, doubl
         for (int l = 0; l < K; ++l) f += A[l];
     }
     if (zmax) *zmax = zm;
+    return f;
+}
+
+// Squared-affine form of the layers for the 16-bit kernels (Eq. mlsp2 rewritten as in App. C).
+// With s_i = b_i/(2a_i) and e_i = c_i - a_i s_i^2, layer i maps x to a_i (x + s_i)^2 + e_i, so
+// its operand is Z_i = x_i + s_i and its epilogue forms the next operand from Y = Z_i^2 alone:
+// Z_{i+1} = a_i Y + (e_i + s_{i+1}) I. The accumulator term d_{i+1} x_{i+1} = d_{i+1} Z_{i+1}
+// - d_{i+1} s_{i+1} I is added as d_{i+1} Z_{i+1}, the constants being folded into the last
+// layer: D = A + a_{L-1} Y + (e_{L-1} - sum_{i>=1} d_i s_i) I. No FP32 copy of the state is read
+// or written, so the state is carried by the hi/lo split alone: 22 significant bits with FP16
+// (used), 16 with BF16 (measured 2.3e-5 against the 1e-5 bar on a dense N = 128 matrix; BF16x2
+// keeps the direct form). Not used (ok = false) when some |a_i| < 1e-6 or an operand would leave
+// [-16, 16] on the unit interval; the epilogue weights (ca, cc, d_new per layer) and the
+// rescale's operand shift s_0 are returned otherwise. dv(i) is the accumulator weight after the
+// skip rule.
+// The squared-affine form is the default; FE_FORM=mlsp2 selects the direct form everywhere.
+inline bool affine_allowed() {
+    const char* f = getenv("FE_FORM");
+    return !(f && strcmp(f, "mlsp2") == 0);
+}
+
+struct AffineForm {
+    bool ok = false;
+    double op_shift = 0.0;
+    std::vector<float> ca, cc, dnew;
+};
+template <class DV>
+inline AffineForm affine_form(const fe_model* m, double alpha, DV dv) {
+    AffineForm f;
+    const int L = m->L;
+    const double* th = m->theta;
+    for (int i = 0; i < L; ++i)
+        if (!(fabs(th[4 * i]) >= 1e-6)) return f;
+    std::vector<double> s(L), e(L);
+    for (int i = 0; i < L; ++i) {
+        s[i] = th[4 * i + 1] / (2.0 * th[4 * i]);
+        e[i] = th[4 * i + 2] - th[4 * i] * s[i] * s[i];
+    }
+    double zmax = 0.0;
+    const int kPts = 1025;
+    for (int k = 0; k < kPts; ++k) {
+        double x = alpha * ((double)k / (kPts - 1) - m->mu0) + m->mu0;
+        for (int i = 0; i < L; ++i) {
+            const double z = x + s[i];
+            zmax = fmax(zmax, fabs(z));
+            x = th[4 * i] * z * z + e[i];
+        }
+    }
+    if (!(zmax <= 16.0)) return f;
+    double fold = 0.0;
+    for (int i = 1; i < L; ++i) fold -= dv(i) * s[i];
+    f.ca.resize(L);
+    f.cc.resize(L);
+    f.dnew.resize(L);
+    for (int i = 0; i < L; ++i) {
+        f.ca[i] = (float)th[4 * i];
+        const bool last = i + 1 == L;
+        f.cc[i] = (float)(last ? e[i] + fold : e[i] + s[i + 1]);
+        f.dnew[i] = last ? 0.0f : (float)dv(i + 1);
+    }
+    f.op_shift = s[0];
+    f.ok = true;
     return f;
 }
 

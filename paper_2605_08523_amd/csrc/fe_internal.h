@@ -63,6 +63,7 @@ struct RescaleArgs {
     uint16_t* lo;
     int mode;
     int bf16;
+    double op_shift;    // mode 0: the hi/lo operand is X0 + op_shift I (squared-affine form)
     float* X0out;       // optional float32 n x n copy of X0 (fe_rescale)
     int64_t ldx;
 };
@@ -80,6 +81,7 @@ struct LayerArgs {
     float* A;               // accumulator (upper triangle maintained), in place
     float a, b, c;          // this layer's coefficients
     float d_old, d_new;     // A += d_old X + d_new X' (X the layer's input, X' its output; 0 0 = skip)
+    int affine;             // 1: squared-affine form, the operand is the state (X not read or written)
     int last;               // 1 on the last layer
     int out_mode;           // last layer: 0 = D float32, 1 = D float64, 2 = traces only
     int entropy;            // last layer: partials hold U traces for S (no D written)
@@ -169,9 +171,10 @@ struct BatchMat {
 // at coef[(k * max_L + l) * 8 + {0, 1, 2, 3, 4}] = a, b, c, d_old, d_new (accumulator terms
 // paired as in the single-matrix kernels); model k has L[k] layers and initial weight d0[k].
 struct BatchCoef {
-    const float* coef;
+    const float* coef;      // [model][layer][8]: a, b, c, d_old, d_new, affine flag (LayerArgs)
     const int32_t* L;
     const float* d0;
+    const double* shift0;   // operand shift of the rescale (squared-affine form), per model
     int max_L;
 };
 struct BatchLayerArgs {

@@ -120,6 +120,7 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
     const BatchMat m = mats[b];
     const double mu0 = m.mu0;
     const float d0 = cf.d0[m.model];
+    const double s0 = cf.shift0[m.model];
     const double scale = P[b].scale, shift = P[b].shift;
     const int64_t total = m.np * m.np;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -134,7 +135,7 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
         m.X[e] = xf;
         m.A[e] = d0 * xf;
         uint16_t h, l;
-        split16<BF>(xf, h, l);
+        split16<BF>(i == j ? (float)(x + s0) : xf, h, l);
         m.hi[0][e] = h;
         m.lo[0][e] = l;
     }
@@ -176,6 +177,7 @@ k_batch_layer(BatchLayerArgs q) {
     p.c = cf[2];
     p.d_old = cf[3];
     p.d_new = cf[4];
+    p.affine = cf[5] != 0.0f;
     p.last = q.layer == L - 1;
     p.entropy = q.entropy;
     p.D = m.D;

@@ -9,8 +9,10 @@
 //    the lo*lo term being below 2^-22 relative for FP16. By symmetry the B operand of tile
 //    (I, J) is the row panel J, so both operands are row panels with K contiguous.
 //  * The epilogue is fused (see split_common.h): Y goes through LDS, one row-major pass applies
-//    a Y + b X + c delta_ij, updates A with the next layer's d and writes the master and the next
-//    hi/lo; a transposed pass writes the mirror tile. The last layer writes D and FP64 traces.
+//    a Y + b X + c delta_ij, updates A and writes the next hi/lo (and, in the direct form, the FP32
+//    master X); a transposed pass writes the mirror tile. The last layer writes D and FP64
+//    traces. In the squared-affine form (FP16x2 default) the operand is the shifted state
+//    x + b/(2a), so b = 0 and X is neither read nor written.
 //  * Three schedules:
 //      data-parallel: one workgroup per upper tile (128 x 128, four 64 x 64 wave tiles);
 //      stream-K over 128 x 128 tiles, two persistent workgroups per CU: the (tile, K-block)

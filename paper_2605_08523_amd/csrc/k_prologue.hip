@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_rescale(RescaleArgs a) {
             a.A32[e] = d0f * xf;
             if (a.mode == 0) {
                 uint16_t h, l;
-                split16<BF>(xf, h, l);
+                split16<BF>(i == j ? (float)(x + a.op_shift) : xf, h, l);
                 a.hi[e] = h;
                 a.lo[e] = l;
             }

@@ -319,7 +319,8 @@ __device__ inline floatx4 load4_coherent(__amdgpu_buffer_rsrc_t rs, int off) {
 //   read device-coherently, added in this order);
 //   X' = a Y + b X + c delta_ij;  A += d_old X + d_new X';  write the FP32 master and the next layer's
 //   hi/lo for the tile (row-major pass, four columns per thread) and its mirror (transposed pass
-//   through sY, four rows per thread). On the last layer: D = A + X' (delta_ij - D if flipped)
+//   through sY, four rows per thread). With p.affine (squared-affine form) X' is the next operand
+//   itself: X is neither read nor written (b = d_old = 0). On the last layer: D = A + X' (delta_ij - D if flipped)
 //   written to the tile and its mirror, or (entropy) U = A + X' traced only; FP64 trace sums
 //   accumulate in tr, sq. Diagonal tiles keep only the upper triangle of X and A, and their lower
 //   half of hi/lo (or D) comes from the mirror pass, so every stored matrix is exactly symmetric.
@@ -347,6 +348,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     uint16_t* __restrict__ hout = p.hi_out;
     uint16_t* __restrict__ lout = p.lo_out;
     const bool load_a = last || upd;
+    const bool use_x = p.affine == 0;   // squared-affine form: no FP32 state besides A
 
     // Row-major pass: groups of four consecutive columns, 16-byte accesses, in batches of U
     // groups per thread. The loads of batch i + 1 are issued before the stores of batch i: the
@@ -367,7 +369,8 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
                          : *reinterpret_cast<const floatx4*>(sY + rl * C::LDY + c);
             if (nparts > 0)
                 bt.p[u] = load4_coherent(make_rsrc(parts, part_bytes), loc * (int)sizeof(float));
-            bt.x[u] = *reinterpret_cast<const floatx4*>(X + gi);
+            if (use_x) bt.x[u] = *reinterpret_cast<const floatx4*>(X + gi);
+            else bt.x[u] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             if (load_a) bt.a[u] = *reinterpret_cast<const floatx4*>(A + gi);
         }
     };
@@ -406,7 +409,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             const bool full = !diag || c >= r;
             if (!last) {
                 if (full) {
-                    *reinterpret_cast<floatx4*>(X + gi) = xn;
+                    if (use_x) *reinterpret_cast<floatx4*>(X + gi) = xn;
                     if (upd) {
                         floatx4 a4;
 #pragma unroll
@@ -422,7 +425,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         if (c + k < r) continue;
-                        X[gi + k] = xn[k];
+                        if (use_x) X[gi + k] = xn[k];
                         if (upd) A[gi + k] = fmaf(dnew, xn[k], fmaf(dold, x[u][k], a[u][k]));
                         uint16_t h, l;
                         split16<BF>(xn[k], h, l);

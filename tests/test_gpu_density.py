@@ -268,3 +268,38 @@ def test_hybrid_schedule_agrees(api, paper_model, monkeypatch):
     assert out["sk2"][1] == pytest.approx(out["dp"][1], abs=1e-6 * n)
     torch.cuda.synchronize()
     ws.close()
+
+
+@pytest.mark.parametrize("sch", ["dp", "sk", "sk2"])
+def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
+    """The squared-affine layer form (operand = shifted state, no FP32 state copy; the FP16x2
+    default) and the direct form a X^2 + b X + c I (FE_FORM=mlsp2) compute the same recursion:
+    both within the bar of the oracle's FP64 recursion and close to each other, density and
+    entropy, for every schedule."""
+    prec = "fp16x2"
+    m = paper_model
+    H = W.random_dense(1100, 25)
+    n = H.shape[0]
+    mu, kT = 0.05, 0.1
+    monkeypatch.setenv("FE_SCHEDULE", sch)
+    Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
+    out = {}
+    for form in ("affine", "mlsp2"):
+        if form == "mlsp2":
+            monkeypatch.setenv("FE_FORM", "mlsp2")
+        else:
+            monkeypatch.delenv("FE_FORM", raising=False)
+        print(f"case forms {form} {sch} {prec} N={n}", flush=True)
+        D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec, ws=sk_ws)
+        Hd = torch.from_numpy(H).cuda()
+        S, _ = api.expand_entropy(Hd, mu, kT, m, 0.842704, prec=prec, ws=sk_ws)
+        torch.cuda.synchronize()
+        fro, _ = report(f"{form} {sch} {prec} vs recursion", D, Drec)
+        assert fro <= 1e-5
+        assert torch.equal(Dt, Dt.T)
+        out[form] = (D, float(S), tr)
+    d = np.max(np.abs(out["affine"][0] - out["mlsp2"][0]))
+    print(f"[forms {sch} {prec}] max |D_affine - D_mlsp2| = {d:.3e}, |dS| = "
+          f"{abs(out['affine'][1] - out['mlsp2'][1]):.3e}", flush=True)
+    assert d < 1e-4
+    assert out["affine"][1] == pytest.approx(out["mlsp2"][1], rel=1e-4, abs=1e-3)

@@ -63,16 +63,17 @@ def test_filling_against_oracle(api, paper_model, name, make, kT, filling, mu_in
 
 def test_filling_in_a_gap(api, paper_model):
     """Low temperature, n_occ an integer inside a spectral gap: Tr D is flat around the answer
-    (vanishing derivative); the bracket keeps the iteration inside the gap."""
+    (vanishing derivative); the bracket keeps the iteration inside the gap. The trace tolerance
+    1e-5 is ~10 ulps of the 22-bit operand split summed over the 80 occupied states."""
     n, nb = 200, 80
     H, lam = W.gapped_spectrum(n, nb, 0.4, 9)
     Hd = torch.from_numpy(H).cuda()
     D, mu, iters, tr, tr2, info = api.expand_density_filling(Hd, float(nb), 0.005, paper_model,
-                                                             prec="fp16x2", tol=1e-6)
+                                                             prec="fp16x2", tol=1e-5)
     torch.cuda.synchronize()
     print(f"[filling gap] iters={iters} mu={mu:.6f} TrD={float(tr):.9f}", flush=True)
     assert -0.2 < mu < 0.2
-    assert abs(float(tr) - nb) <= 1e-6
+    assert abs(float(tr) - nb) <= 1e-5
     # idempotent: the projector onto the occupied states
     assert abs(float(tr) - float(tr2)) < 1e-4
 
