@@ -50,6 +50,9 @@ def parse():
                         "density and entropy")
     p.add_argument("--model", default="bank",
                    help="anderson4096: 'bank' (select per matrix, default) or one model name")
+    p.add_argument("--vendor-gemm", action="store_true",
+                   help="only the vendor FP16 GEMM (torch.matmul) on a plain 4096^3 product, 20 "
+                        "times (the reference for the layer kernel's MFMA counters)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only a plain 1 GiB device-to-device copy, three times (the reference for "
                         "scaling the HBM byte counters)")
@@ -113,6 +116,14 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print("copy calibration done: 3 copies of 1 GiB", flush=True)
+        return
+    if args.vendor_gemm:
+        n = 4096
+        ga = torch.randn(n, n, device=dev, dtype=torch.float16)
+        gb = torch.randn(n, n, device=dev, dtype=torch.float16).t().contiguous()
+        ms = timed(lambda: ga @ gb, 20, 3, torch)
+        print(f"vendor fp16 gemm {n}^3: {ms * 1e3:.1f} us, {2.0 * n ** 3 / ms / 1e9:.1f} TFLOP/s",
+              flush=True)
         return
     if args.workload == "batch1024":
         return bench_batch(args, torch, api, models, workloads, dev)
