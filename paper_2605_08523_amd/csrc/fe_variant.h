@@ -42,9 +42,18 @@ hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
 int combine_tiles(int64_t np);   // upper 64 x 64 tiles (= trace partials written by out = 1)
 
 // out = Z^2 for Z = hi + lo / s (split operand), FP32, upper 128 x 128 tiles, elements on or
-// above the diagonal; np a multiple of 128.
+// above the diagonal; np a multiple of 128. Whole rounds of `slots` tiles run data-parallel; a
+// small last round (at most slots / 4 tiles) is split along K over the slots, its partials
+// (parts: at most slots tiles of 128 x 128 floats) added in a fixed order.
+struct SquareSplit {
+    int dp = 0;       // tiles of the data-parallel launch
+    int tail = 0;     // tiles split along K
+    int nsplit = 0;   // segments per split tile
+};
+SquareSplit square_split(int ntiles, int nk, int slots);
+constexpr int64_t kSquarePartTile = 128 * 128;   // floats per partial tile
 hipError_t launch_square(const uint16_t* hi, const uint16_t* lo, int64_t np, float* out, int bf16,
-                         hipStream_t s);
+                         int slots, float* parts, hipStream_t s);
 
 // Scalar Skip-SP2 / Max-SP2 model at n device points and, if JT is not null, its Jacobian
 // transposed (JT[p][k], coefficient p in the layout of fe_qmodel). coef is a device array.

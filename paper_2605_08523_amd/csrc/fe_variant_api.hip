@@ -19,9 +19,20 @@ int variant_slots(const fe_qmodel* m) {
     return m->arch == FE_ARCH_MAX ? m->L + 1 : m->k + m->K;
 }
 
-int64_t variant_bytes(int64_t np, const fe_qmodel* m) {
+// Workgroup slots of one data-parallel round of the squaring (two per CU) on the current device.
+int square_slots() {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return 2 * ncu;
+}
+
+// States, the hi/lo operand and the squaring's partial tiles (one round of slots at most).
+int64_t variant_bytes(int64_t np, const fe_qmodel* m, int slots) {
     const int64_t e = np * np;
-    return (int64_t)variant_slots(m) * e * (int64_t)sizeof(float) + 2 * e * (int64_t)sizeof(uint16_t);
+    return (int64_t)variant_slots(m) * e * (int64_t)sizeof(float) + 2 * e * (int64_t)sizeof(uint16_t) +
+           (int64_t)slots * fe::kSquarePartTile * (int64_t)sizeof(float);
 }
 
 // Largest |operand| over the unit interval of the model coordinate (4097 points).
@@ -52,7 +63,7 @@ int fe_variant_scratch_bytes(int64_t n, const fe_qmodel* m, int64_t* bytes) {
     if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
     int rc = check_qmodel(m);
     if (rc) return rc;
-    *bytes = variant_bytes(round_up(n, kVarTile), m);
+    *bytes = variant_bytes(round_up(n, kVarTile), m, square_slots());
     return FE_OK;
 }
 
@@ -68,7 +79,8 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
         return fail(FE_ERR_ARG, "the Skip-SP2 / Max-SP2 path runs the 16-bit split modes only");
     if (D && ldd < n) return fail(FE_ERR_ARG, "ldd < n");
     const int64_t np = round_up(n, kVarTile);
-    if (!scratch || scratch_bytes < variant_bytes(np, m))
+    const int slots = square_slots();
+    if (!scratch || scratch_bytes < variant_bytes(np, m, slots))
         return fail(FE_ERR_WORKSPACE, "scratch is smaller than fe_variant_scratch_bytes");
     if (fe::combine_tiles(np) > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
     if (variant_range(m) > 16.0) return fail(FE_ERR_RANGE, "operands exceed the 16-bit operand range");
@@ -79,6 +91,7 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
     for (size_t q = 0; q < slot.size(); ++q) slot[q] = static_cast<float*>(scratch) + q * e;
     uint16_t* hi = reinterpret_cast<uint16_t*>(static_cast<float*>(scratch) + slot.size() * e);
     uint16_t* lo = hi + e;
+    float* parts = reinterpret_cast<float*>(lo + e);
 
     fe::Params* P = ws->params;
     FE_HIP(fe::launch_bounds_params(H, n, ldh, mu, kT, m->beta0, m->mu0, ws->bparts, P, s));
@@ -109,7 +122,7 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
                 a.w[j] = (float)c[off + 1 + j];
             }
             FE_HIP(fe::launch_combine(a, s));
-            FE_HIP(fe::launch_square(hi, lo, np, slot[i + 1], bf, s));
+            FE_HIP(fe::launch_square(hi, lo, np, slot[i + 1], bf, slots, parts, s));
             off += i + 2;
         }
         fin.diag = (float)c[off];
@@ -146,7 +159,7 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
             a.acc_src = ring[i % k];
             a.acc_first = i == 0;
             FE_HIP(fe::launch_combine(a, s));
-            FE_HIP(fe::launch_square(hi, lo, np, ring[(i + 1) % k], bf, s));
+            FE_HIP(fe::launch_square(hi, lo, np, ring[(i + 1) % k], bf, slots, parts, s));
         }
         double d = 0.0;
         for (int l = 0; l < K; ++l) d += a0[l];

@@ -11,6 +11,8 @@
 //    use it forms the result f and writes D with FP64 trace partials.
 // The scalar kernel evaluates the same models at sample points with a reverse-mode Jacobian
 // (FP64, one lane per point) for the coefficient trainer.
+#include <algorithm>
+
 #include "fe_variant.h"
 #include "split_common.h"
 
@@ -55,6 +57,74 @@ k_square(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64
                 if (!diag || c >= r) out[(I0 + r) * np + J0 + c] = acc.v[mb][nb][j] * inv_s;
             }
         }
+}
+
+// The tiles left after the whole rounds of the data-parallel launch (a partial round would
+// leave most CUs idle): tile tile0 + w / nsplit, K-blocks of segment w % nsplit, its FP32 partial
+// (row-major 128 x 128) to parts[w]; k_square_reduce adds the nsplit partials of each tile in
+// segment order and stores the elements on or above the diagonal.
+template <bool BF, class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_square_part(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t np,
+              int tile0, int nsplit, float* __restrict__ parts) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int T = (int)(np / C::BM);
+    const int w = blockIdx.x;
+    int I, J;
+    tile_coords(tile0 + w / nsplit, T, I, J);
+    const int nk = (int)(np / C::BK), sg = w % nsplit;
+    const int kb0 = (int)((int64_t)sg * nk / nsplit), kb1 = (int)((int64_t)(sg + 1) * nk / nsplit);
+    Acc<C> acc;
+#pragma unroll
+    for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc.v[mb][nb][j] = 0.0f;
+    kloop<BF, C>(hi, lo, np, (int64_t)I * C::BM, (int64_t)J * C::BM, kb0, kb1, acc,
+                 reinterpret_cast<uint16_t*>(smem));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const float inv_s = BF ? 1.0f : (1.0f / 2048.0f);
+    float* out = parts + (size_t)w * C::BM * C::BM;
+#pragma unroll
+    for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+            const int c = wn * C::WAVE_N + nb * 32 + (lane & 31);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int r = wm * C::WAVE_M + mb * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+                out[r * C::BM + c] = acc.v[mb][nb][j] * inv_s;
+            }
+        }
+}
+
+// One block per 1024 elements (256 threads x 4) of a split tile: kReduceBlocks blocks per tile.
+constexpr int kReduceBlocks = 128 * 128 / 1024;
+
+template <class C>
+__global__ void __launch_bounds__(256)
+k_square_reduce(int64_t np, int tile0, int nsplit, const float* __restrict__ parts,
+                float* __restrict__ out) {
+    const int T = (int)(np / C::BM);
+    const int tl = blockIdx.x / kReduceBlocks;
+    int I, J;
+    tile_coords(tile0 + tl, T, I, J);
+    const bool diag = I == J;
+    const float* p = parts + (size_t)tl * nsplit * C::BM * C::BM;
+    {
+        const int e = (blockIdx.x % kReduceBlocks) * 1024 + threadIdx.x * 4;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < nsplit; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] += p[(size_t)q * C::BM * C::BM + e + k];
+        const int r = e / C::BM, c = e % C::BM;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (!diag || c + k >= r)
+                out[((int64_t)I * C::BM + r) * np + (int64_t)J * C::BM + c + k] = v[k];
+    }
 }
 
 constexpr int kCT = 64;   // combine tile
@@ -324,14 +394,24 @@ hipError_t set_lds_once(Kern kern, size_t bytes, bool& done) {
 
 template <bool BF>
 hipError_t launch_square_t(const uint16_t* hi, const uint16_t* lo, int64_t np, float* out,
-                           hipStream_t s) {
+                           int slots, float* parts, hipStream_t s) {
     using C = CfgQ;
     auto kern = k_square<BF, C>;
-    static bool done = false;
+    auto kpart = k_square_part<BF, C>;
+    static bool done = false, done_p = false;
     hipError_t e = set_lds_once(kern, C::LDS_BYTES, done);
+    if (e == hipSuccess) e = set_lds_once(kpart, C::LDS_BYTES, done_p);
     if (e != hipSuccess) return e;
-    const int T = (int)(np / C::BM);
-    hipLaunchKernelGGL(kern, dim3(T * (T + 1) / 2), dim3(C::NT), C::LDS_BYTES, s, hi, lo, np, out);
+    const int T = (int)(np / C::BM), ntiles = T * (T + 1) / 2, nk = (int)(np / C::BK);
+    SquareSplit sp = square_split(ntiles, nk, slots);
+    if (sp.dp > 0)
+        hipLaunchKernelGGL(kern, dim3(sp.dp), dim3(C::NT), C::LDS_BYTES, s, hi, lo, np, out);
+    if (sp.tail > 0) {
+        hipLaunchKernelGGL(kpart, dim3(sp.tail * sp.nsplit), dim3(C::NT), C::LDS_BYTES, s, hi, lo,
+                           np, sp.dp, sp.nsplit, parts);
+        hipLaunchKernelGGL(k_square_reduce<C>, dim3(sp.tail * kReduceBlocks), dim3(256), 0, s, np,
+                           sp.dp, sp.nsplit, (const float*)parts, out);
+    }
     return hipGetLastError();
 }
 
@@ -354,10 +434,25 @@ hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+SquareSplit square_split(int ntiles, int nk, int slots) {
+    SquareSplit sp;
+    const int rounds = slots > 0 ? ntiles / slots : 0;
+    const int tail = ntiles - rounds * slots;
+    if (rounds >= 1 && tail > 0 && 4 * tail <= slots) {
+        sp.dp = rounds * slots;
+        sp.tail = tail;
+        sp.nsplit = std::min(slots / tail, nk);
+    } else {
+        sp.dp = ntiles;
+    }
+    return sp;
+}
+
 hipError_t launch_square(const uint16_t* hi, const uint16_t* lo, int64_t np, float* out, int bf16,
-                         hipStream_t s) {
+                         int slots, float* parts, hipStream_t s) {
     if (np % CfgQ::BM != 0) return hipErrorInvalidValue;
-    return bf16 ? launch_square_t<true>(hi, lo, np, out, s) : launch_square_t<false>(hi, lo, np, out, s);
+    return bf16 ? launch_square_t<true>(hi, lo, np, out, slots, parts, s)
+                : launch_square_t<false>(hi, lo, np, out, slots, parts, s);
 }
 
 hipError_t launch_variant_eval(const VariantEvalArgs& a, hipStream_t s) {

@@ -221,3 +221,26 @@ def test_trainer_from_embedding(var):
     m = V.unflatten(fit.coef, V.skip_to_max(V.mlsp2_to_skip(th)))
     err = np.max(np.abs(V.evaluate(y, m) - OT.fermi_target(y, 40.0, 0.3)))
     assert err <= rep["max_err_grid"] * 1.01
+
+
+def test_full_size_tail_split(var):
+    """N = 4096: 528 upper tiles of 128 on 512 workgroup slots, so the squaring runs one
+    data-parallel round and splits the 16 remaining tiles along K (partials added in a fixed
+    order). Property check at the headline size: the Skip-SP2 embedding equals the MLSP2 path
+    (itself checked against the oracle at this size) and a second run is bitwise identical."""
+    from paper_2605_08523_amd import api, models
+    base = models.load("mlsp2_L22_b600_mu1third")
+    c = W.config_anderson_4096()
+    Hd = torch.from_numpy(c["H"]).cuda()
+    qm = var.embed_mlsp2(base, "skip")
+    print("case tail split skip N=4096", flush=True)
+    D1, tr1, _, _ = var.expand_density_variant(Hd, c["mu"], c["kT"], qm)
+    D2, _, _, _ = var.expand_density_variant(Hd, c["mu"], c["kT"], qm)
+    Dm, trm, _, _ = api.expand_density(Hd, c["mu"], c["kT"], base)
+    torch.cuda.synchronize()
+    d = float((D1 - Dm).abs().max())
+    print(f"[tail split] max |D_skip - D_mlsp2| = {d:.3e}, dTr = {abs(float(tr1) - float(trm)):.3e}",
+          flush=True)
+    assert torch.equal(D1, D2)
+    assert d < 1e-5
+    assert abs(float(tr1) - float(trm)) < 1e-5 * 4096
