@@ -76,14 +76,15 @@ def timed(fn, steps, warmup, torch):
 
 KERNEL_SOURCES = ("fe_api.hip", "fe_internal.h", "k_layer_split.hip", "split_common.h")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_counters_anderson4096.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_sq_counters_anderson4096.md")
 
 
-def measured_traffic():
-    """HBM bytes per layer launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
-    (copy-calibrated), or None if the layer kernel's sources changed since it was taken."""
+def _profile_record(path, tag):
+    """The JSON record after `tag:` in a committed profile summary, or None if it is missing or
+    the layer kernel's sources changed since the counters were taken (SHA-256 over them)."""
     import hashlib
     try:
-        line = next(l for l in open(COUNTER_SUMMARY) if l.startswith("traffic_json:"))
+        line = next(l for l in open(path) if l.startswith(tag + ":"))
         rec = json.loads(line.split(":", 1)[1])
     except (OSError, StopIteration, ValueError):
         return None
@@ -91,9 +92,21 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2605_08523_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != rec.get("source_sha256"):
-        return None
-    return rec["bytes_per_launch"]
+    return rec if h.hexdigest() == rec.get("source_sha256") else None
+
+
+def measured_traffic():
+    """HBM bytes per layer launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
+    (copy-calibrated), or None if the layer kernel's sources changed since it was taken."""
+    rec = _profile_record(COUNTER_SUMMARY, "traffic_json")
+    return rec["bytes_per_launch"] if rec else None
+
+
+def measured_pipe_busy():
+    """Clock and MFMA-pipe occupancy of the layer kernel from the committed SQ-counter summary
+    (None if stale)."""
+    rec = _profile_record(SQ_SUMMARY, "sq_json")
+    return {k: rec[k] for k in ("clock_ghz", "mfma_pipe_busy", "vendor_gemm_mfma_pipe_busy")} if rec else None
 
 
 def main():
@@ -218,10 +231,18 @@ def main():
             "layer_ms": layer_ms,
             "executed_mfma_tflops": exec_flop_layer / (layer_ms * 1e-3) / 1e12,
             "executed_frac": exec_flop_layer / (layer_ms * 1e-3) / 1e12 / peak,
+            "sq_counters": measured_pipe_busy(),
             "method": f"HIP events on the launch stream: (t(L={L}) - t(L=1)) / {L - 1}",
         },
         "prologue_plus_one_layer_ms": ms1,
     }
+    # the whole single-matrix path of Alg. 2: density and entropy (theta_fermi reused for S,
+    # alpha = 0.842704, as in the paper's Table I rows with theta_fermi)
+    ms_ds = timed(lambda: (step(), api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec,
+                                                      ws=ws)),
+                  args.steps, args.warmup, torch)
+    out["step_with_entropy"] = {"ms": ms_ds, "per_s": 1000.0 / ms_ds,
+                                "what": "model selection + density + entropy expansion"}
     if bank is not None:
         out["expand_only_ms"] = ms_expand
         m26 = models.load("mlsp2_L26_b1500_mu1third")
