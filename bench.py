@@ -535,6 +535,15 @@ def bench_variants(args, torch, api, models, workloads, dev):
             r["error_vs_oracle_fro_over_N"] = float(np.linalg.norm(D.double().cpu().numpy() -
                                                                    ref["D"]) / n)
         res[k] = r
+    # per-layer time of the Skip-SP2 path (square + combine; constant per layer) by the same
+    # difference as the headline: (t(L layers) - t(1 layer)) / (L - 1), HIP events on the stream
+    q1 = variants.embed_mlsp2(api.make_model(base.theta[-1:], base.beta0, base.mu0), "skip")
+    ms1 = timed(lambda: variants.expand_density_variant(Hd, mu, kT, q1, prec=args.prec, out=D,
+                                                        scratch=scratch["skip"], ws=ws),
+                args.steps, args.warmup, torch)
+    L = fams["skip"].L
+    layer_ms = (res["skip"]["ms_per_step"] - ms1) / (L - 1)
+    achieved = 2.0 * n ** 3 / (layer_ms * 1e-3) / 1e12
     out = {"metric": "density matrices/s, Skip-SP2 / Max-SP2 embeddings of the selected model",
            "value": res["skip"]["value"], "unit": "density matrices/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["skip"]["ms_per_step"],
@@ -543,7 +552,13 @@ def bench_variants(args, torch, api, models, workloads, dev):
            "config": {"workload": "anderson_cubic_16x16x16_periodic_N4096_t-1_W1_kT0.05_mu0",
                       "N": n, "model": "App. C embedding of mlsp2_L22_b600_mu1third",
                       "precision": args.prec},
-           "skip_sp2_k1_K1": res["skip"], "max_sp2": res["max"], "fused_mlsp2_ms": ms_m}
+           "skip_sp2_k1_K1": res["skip"], "max_sp2": res["max"], "fused_mlsp2_ms": ms_m,
+           "roofline": {"kernel": "Skip-SP2 layer: k_square (split MFMA square, K-split last "
+                                  "round) + k_combine", "bound": "mfma", "achieved": achieved,
+                        "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_TFLOPS[args.prec], "traffic": None,
+                        "layer_ms": layer_ms,
+                        "method": f"HIP events: (t(L={L}) - t(L=1)) / {L - 1}, algorithmic 2 N^3"}}
     print(json.dumps(out), flush=True)
 
 

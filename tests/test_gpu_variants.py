@@ -244,3 +244,32 @@ def test_full_size_tail_split(var):
     assert torch.equal(D1, D2)
     assert d < 1e-5
     assert abs(float(tr1) - float(trm)) < 1e-5 * 4096
+
+
+def test_skip_trainer_from_embedding(var):
+    """Skip-SP2 with two skips (k = 2, K = 1) fine-tuned from the embedding of a 10-layer MLSP2
+    fit (the extra skip weights start at zero): no accuracy lost, some gained, and the oracle
+    evaluates the fitted model to the error the trainer reports."""
+    from paper_2605_08523_amd import api, training
+    from oracle import training as OT
+    th, rep0, _ = training.train_coeffs(10, 40.0, 0.3, n_points=4096, max_iter=300, tol=1e-12)
+    e11 = var.embed_mlsp2(api.make_model(th, 40.0, 0.3), "skip").coef
+    L = 10
+    per1, per2 = 4, 5
+    c = np.zeros(per2 * L + 2)
+    for i in range(L):
+        a_c, a0, b, g = e11[per1 * i:per1 * (i + 1)]
+        c[per2 * i:per2 * (i + 1)] = (a_c, a0, 0.0, b, g)
+    c[per2 * L:] = e11[per1 * L:]
+    init = var.QModel("skip", L, c, 40.0, 0.3, k=2, K=1)
+    fit, rep, _ = var.train_variant(init, 40.0, 0.3, n_points=4096, max_iter=100, tol=1e-14)
+    print(f"[skip-sp2 k2 L10] grid max err {rep['max_err_grid']:.3e} (MLSP2 {rep0['max_err_grid']:.3e})",
+          flush=True)
+    assert rep["max_err_grid"] <= rep0["max_err_grid"] * 1.0001
+    assert rep["max_err_grid"] < rep0["max_err_grid"]
+    like = V.unflatten(c, {"kind": "skip", "k": 2, "K": 1, "alpha_c": np.zeros(L),
+                           "alpha": np.zeros((L, 2)), "beta": np.zeros((L, 1)),
+                           "gamma": np.zeros((L, 1)), "a0": np.zeros(1), "omega": 0.0})
+    y = np.linspace(0, 1, 20001)
+    err = np.max(np.abs(V.evaluate(y, V.unflatten(fit.coef, like)) - OT.fermi_target(y, 40.0, 0.3)))
+    assert err <= rep["max_err_grid"] * 1.01
