@@ -261,9 +261,10 @@ inline AffineForm affine_form(const fe_model* m, double alpha, DV dv) {
 
 // Accumulator schedule of the 16-bit layer kernels in the direct form (BF16x2, or FP16x2 with
 // FE_FORM=mlsp2; the squared-affine form adds one term per layer). The recursion adds d_j X_j
-// for j = 1 .. L-1 (d_0 X_0 is formed by the rescale; X_L is the output). Layer i's epilogue sees X_i (its input)
-// and X_{i+1} (its output), so each term can be added by one of two layers; terms are paired,
-// A += d_j X_j + d_{j+1} X_{j+1} at layer j, which halves the layers that read and write A.
+// for j = 1 .. L-1 (d_0 X_0 is formed by the rescale; X_L is the output). Layer i's epilogue sees
+// X_i (its input) and X_{i+1} (its output), so each term can be added by one of two layers; terms
+// are paired, A += d_j X_j + d_{j+1} X_{j+1} at layer j, which halves the layers that read and
+// write A.
 // dv(j) is d_j after the skip rule; d_old[i], d_new[i] are layer i's weights of X_i, X_{i+1}.
 template <class DV>
 inline void pair_accumulator_terms(int L, DV dv, std::vector<float>& d_old, std::vector<float>& d_new) {
