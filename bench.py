@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
     p.add_argument("--workload", default="anderson4096",
                    choices=["anderson4096", "batch1024", "large16384", "filling4096",
-                            "variants4096"],
+                            "variants4096", "sweep"],
                    help="anderson4096: the headline line (default); batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
                         "density and entropy")
@@ -146,6 +146,8 @@ def main():
         return bench_filling(args, torch, api, models, workloads, dev)
     if args.workload == "variants4096":
         return bench_variants(args, torch, api, models, workloads, dev)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, api, models, workloads, dev)
     c = workloads.config_anderson_4096()
     H = c["H"]
     n = H.shape[0]
@@ -251,6 +253,20 @@ def main():
                      args.steps, args.warmup, torch)
         out["fixed_model_L26"] = {"coefficients": m26.name, "ms_per_step": ms26,
                                   "value": 1000.0 / ms26}
+    # the squared-affine layer form (opt-in, FE_FORM=affine): same step, its own error below
+    Daff = None
+    if args.prec == "fp16x2":
+        os.environ["FE_FORM"] = "affine"
+        try:
+            ms_aff = timed(step, args.steps, args.warmup, torch)
+            api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws)
+            torch.cuda.synchronize()
+            Daff = D.double().cpu().numpy()
+        finally:
+            del os.environ["FE_FORM"]
+        out["affine_form"] = {"ms_per_step": ms_aff, "value": 1000.0 / ms_aff,
+                              "what": "FE_FORM=affine: operand = shifted state, no FP32 state "
+                                      "traffic in the epilogue"}
     # the timed runs end with the one-layer model: recompute D with the full model for the error
     _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws,
                                             want_info=True)
@@ -311,6 +327,8 @@ def main():
                                   "max_abs": float(np.max(np.abs(err))),
                                   "abs_dTrD": abs(float(trD) - ref["trD"]),
                                   "abs_dTrD2": abs(float(trD2) - ref["trD2"])}
+        if Daff is not None:
+            out["affine_form"]["fro_over_N_vs_oracle"] = float(np.linalg.norm(Daff - ref["D"]) / n)
     print(json.dumps(out), flush=True)
 
 
@@ -559,6 +577,58 @@ def bench_variants(args, torch, api, models, workloads, dev):
                         "frac": achieved / PEAK_TFLOPS[args.prec], "traffic": None,
                         "layer_ms": layer_ms,
                         "method": f"HIP events: (t(L={L}) - t(L=1)) / {L - 1}, algorithmic 2 N^3"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, torch, api, models, workloads, dev):
+    """The paper's timing experiment (Sec. V.D): wall clock of a 26-layer evaluation with the
+    printed (beta0 = 1500, mu0 = 1/3) model on random dense symmetric matrices of growing N,
+    against diagonalization-based density matrices (FP64 and FP32 eigh + V f V^T) on the same
+    GPU. kT is set per matrix so that beta' = 600 (inside the model's validity, beta' <= 1000),
+    mu at the middle of the Gershgorin interval. Errors against the FP64 diagonalization."""
+    import numpy as np
+    m = models.load("mlsp2_L26_b1500_mu1third")
+    mref = api.make_model(m.theta, m.beta0, m.mu0)
+    rows = []
+    for n in (256, 512, 1024, 2048, 4096, 8192):
+        H = workloads.random_dense(n, 50 + n)
+        r = np.abs(H).sum(axis=1) - np.abs(np.diag(H))
+        lo, hi = float(np.min(np.diag(H) - r)), float(np.max(np.diag(H) + r))
+        mu, kT = 0.5 * (lo + hi), (hi - lo) / 600.0
+        Hd = torch.from_numpy(H).to(dev)
+        ws = api.Workspace(n)
+        D = torch.empty((n, n), dtype=torch.float32, device=dev)
+        steps = max(2, min(args.steps, 10))
+        ms = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws),
+                   steps, 1, torch)
+
+        def eig(dtype):
+            Hc = Hd.to(dtype)
+            w, V = torch.linalg.eigh(Hc)
+            f = torch.sigmoid(-(w - mu) / kT)
+            return (V * f) @ V.T
+        reps = 2 if n >= 4096 else 3
+        ms64 = timed(lambda: eig(torch.float64), reps, 1, torch)
+        ms32 = timed(lambda: eig(torch.float32), reps, 1, torch)
+        D64 = eig(torch.float64)
+        D32 = eig(torch.float32)
+        torch.cuda.synchronize()
+        rows.append({"N": n, "ms": ms, "tflops_algorithmic": m.L * 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+                     "eigh_fp64_ms": ms64, "eigh_fp32_ms": ms32,
+                     "speedup_vs_eigh_fp64": ms64 / ms, "speedup_vs_eigh_fp32": ms32 / ms,
+                     "fro_over_N_vs_eigh_fp64": float(torch.linalg.norm(D.double() - D64).item() / n),
+                     "fro_over_N_eigh_fp32_vs_fp64": float(torch.linalg.norm(D32.double() - D64).item() / n)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        ws.close()
+        del Hd, D, D64, D32
+        torch.cuda.empty_cache()
+    out = {"metric": "ms per density matrix vs N (26 layers) and speedup over eigh",
+           "value": rows[-2]["speedup_vs_eigh_fp64"], "unit": "x vs FP64 eigh at N = 4096",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f16" if args.prec == "fp16x2" else "bf16",
+           "data": "synthetic",
+           "config": {"workload": "random_dense_sweep_N256-8192_beta600", "layers": m.L,
+                      "coefficients": m.name, "precision": args.prec},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

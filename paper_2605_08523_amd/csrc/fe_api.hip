@@ -136,8 +136,8 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
         ra.X32 = b.X; ra.A32 = b.A; ra.hi = b.hi[0]; ra.lo = b.lo[0];
         ra.mode = 0; ra.bf16 = bf;
-        // squared-affine layers for FP16x2 unless FE_FORM=mlsp2 or the coefficients do not allow
-        // them; BF16x2 keeps the FP32 state (its 16-bit split would carry the state alone)
+        // squared-affine layers on request (FE_FORM=affine, FP16x2, coefficients permitting);
+        // BF16x2 always keeps the FP32 state (its 16-bit split would carry the state alone)
         AffineForm af;
         if (!bf && affine_allowed()) af = affine_form(m, alpha, dval);
         ra.op_shift = af.ok ? af.op_shift : 0.0;

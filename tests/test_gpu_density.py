@@ -272,10 +272,10 @@ def test_hybrid_schedule_agrees(api, paper_model, monkeypatch):
 
 @pytest.mark.parametrize("sch", ["dp", "sk", "sk2"])
 def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
-    """The squared-affine layer form (operand = shifted state, no FP32 state copy; the FP16x2
-    default) and the direct form a X^2 + b X + c I (FE_FORM=mlsp2) compute the same recursion:
-    both within the bar of the oracle's FP64 recursion and close to each other, density and
-    entropy, for every schedule."""
+    """The squared-affine layer form (operand = shifted state, no FP32 state copy; FE_FORM=affine)
+    and the direct form a X^2 + b X + c I (the default) compute the same recursion: both within
+    the bar of the oracle's FP64 recursion and close to each other, density and entropy, for
+    every schedule."""
     prec = "fp16x2"
     m = paper_model
     H = W.random_dense(1100, 25)
@@ -285,8 +285,8 @@ def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
     Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
     out = {}
     for form in ("affine", "mlsp2"):
-        if form == "mlsp2":
-            monkeypatch.setenv("FE_FORM", "mlsp2")
+        if form == "affine":
+            monkeypatch.setenv("FE_FORM", "affine")
         else:
             monkeypatch.delenv("FE_FORM", raising=False)
         print(f"case forms {form} {sch} {prec} N={n}", flush=True)
