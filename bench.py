@@ -164,6 +164,8 @@ def main():
         m = models.load(args.model)
     mref = api.make_model(m.theta, m.beta0, m.mu0)
     m1 = api.make_model(m.theta[-1:], m.beta0, m.mu0)      # one layer: prologue + one layer
+    # tile shape / schedule for this size from the autotuner (recorded for the timed runs)
+    tuned = api.autotune([n], prec=args.prec, ws=ws)[0] if not args.profile else None
 
     def expand():
         api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws)
@@ -237,6 +239,7 @@ def main():
             "method": f"HIP events on the launch stream: (t(L={L}) - t(L=1)) / {L - 1}",
         },
         "prologue_plus_one_layer_ms": ms1,
+        "autotune": tuned,
     }
     # the whole single-matrix path of Alg. 2: density and entropy (theta_fermi reused for S,
     # alpha = 0.842704, as in the paper's Table I rows with theta_fermi)

@@ -274,6 +274,28 @@ int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_
                        const float* G, float* work, double* part, int32_t nblocks,
                        double* grad, void* stream);
 
+/* ---- schedule autotuner -------------------------------------------------------------------- */
+
+/* Chooses the tile shape and schedule of the 16-bit layer kernel per matrix size on this device:
+ * 0 = 128 x 128 tiles, one workgroup per upper tile; 1 = 256 x 256 tiles, stream-K over one
+ * workgroup per CU; 2 = 128 x 128 tiles, stream-K over two workgroups per CU (1 and 2 need a
+ * workspace with max_n >= 1536). Each candidate runs a short expansion (1 warm-up + 3 timed, HIP
+ * events on the stream) of a device-generated random symmetric matrix of each size; the fastest
+ * is recorded process-wide for (device, prec, size). Later expansions of a size within a factor
+ * sqrt(2) of a tuned one use its schedule (FE_SCHEDULE still overrides). sizes: host, count
+ * entries, each <= ws max_n. choice (host, count, may be NULL) receives the chosen schedules, ms
+ * (host, 3 x count, may be NULL) each candidate's time per expansion (NaN if not run). prec:
+ * FE_PREC_FP16X2 or FE_PREC_BF16X2. Allocates one n_max x n_max FP64 matrix for the call;
+ * synchronizes. */
+int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choice, double* ms,
+                fe_workspace* ws, void* stream);
+
+/* The schedule an expansion of size n with precision prec on ws would use now (host out). */
+int fe_autotune_lookup(int64_t n, int32_t prec, fe_workspace* ws, int32_t* schedule);
+
+/* Forgets every tuned entry (the size policy applies again). */
+int fe_autotune_clear(void);
+
 /* ---- Skip-SP2 and Max-SP2 (Sec. III.A) ------------------------------------------------- */
 
 #define FE_ARCH_MAX   1   /* Max-SP2 (Eq. maxsp2, Alg. maxsp2-1d) */

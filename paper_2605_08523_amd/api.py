@@ -84,6 +84,9 @@ SIGNATURES = {
     "fe_matrix_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
     "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
+    "fe_autotune": (_I32, [C.POINTER(_I64), _I32, _I32, C.POINTER(_I32), C.POINTER(_D), _P, _P]),
+    "fe_autotune_lookup": (_I32, [_I64, _I32, _P, C.POINTER(_I32)]),
+    "fe_autotune_clear": (_I32, []),
     "fe_qmodel_coef_count": (_I32, [_I32, _I32, _I32, _I32, C.POINTER(_I64)]),
     "fe_variant_scratch_bytes": (_I32, [_I64, C.POINTER(fe_qmodel), C.POINTER(_I64)]),
     "fe_expand_density_variant": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_qmodel), _I32, _P,
@@ -286,6 +289,33 @@ def select_model(H, mu: float, kT: float, bank, ws: Workspace | None = None) -> 
     _check(lib().fe_model_select(C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), structs,
                                  len(refs), C.byref(idx), ws.handle, _stream_ptr()))
     return idx.value
+
+
+SCHEDULES = {0: "dp128", 1: "sk256", 2: "sk2x128"}
+
+
+def autotune(sizes, prec: str = "fp16x2", ws: Workspace | None = None):
+    """fe_autotune: per size, the chosen schedule name and each candidate's ms per expansion."""
+    sizes = [int(x) for x in sizes]
+    ws = ws or workspace(max(sizes))
+    arr = (C.c_int64 * len(sizes))(*sizes)
+    choice = (C.c_int32 * len(sizes))()
+    ms = (C.c_double * (3 * len(sizes)))()
+    _check(lib().fe_autotune(arr, len(sizes), PREC[prec], choice, ms, ws.handle, _stream_ptr()))
+    return [{"n": n, "schedule": SCHEDULES[choice[i]],
+             "ms": {SCHEDULES[c]: ms[3 * i + c] for c in range(3) if ms[3 * i + c] == ms[3 * i + c]}}
+            for i, n in enumerate(sizes)]
+
+
+def autotune_lookup(n: int, prec: str = "fp16x2", ws: Workspace | None = None) -> str:
+    ws = ws or workspace(n)
+    out = C.c_int32()
+    _check(lib().fe_autotune_lookup(int(n), PREC[prec], ws.handle, C.byref(out)))
+    return SCHEDULES[out.value]
+
+
+def autotune_clear() -> None:
+    _check(lib().fe_autotune_clear())
 
 
 def observable(D, A, ws: Workspace | None = None):

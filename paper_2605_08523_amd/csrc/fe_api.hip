@@ -5,7 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "fe_internal.h"
 
@@ -26,14 +28,44 @@ constexpr int64_t kStreamKMinN = 1536;   // workspaces for n >= this carry strea
 //  1 stream-K over 256 x 256 tiles, one workgroup per CU;
 //  2 stream-K over 128 x 128 tiles, two workgroups per CU (whole-tile rounds first when there
 //    are two or more rounds).
-// Default: 2 when every stream-K workgroup gets at least eight K-blocks (else the partial-tile
+// Order: a schedule forced by the tuner, FE_SCHEDULE, the tuned table (fe_autotune), then the
+// default: 2 when every stream-K workgroup gets at least eight K-blocks (else the partial-tile
 // traffic outweighs the balance: measured slower below N ~ 2000), otherwise 0. Only workspaces
 // sized for n >= kStreamKMinN carry the stream-K buffers.
-int use_streamk(int64_t n, const fe_workspace* ws) {
+// Schedules chosen by fe_autotune: (device, precision, size) -> schedule, process-wide. A
+// size uses the entry of the nearest tuned size within a factor sqrt(2).
+struct TunedEntry {
+    int device, prec;
+    int64_t n;
+    int schedule;
+};
+std::mutex g_tune_mu;
+std::vector<TunedEntry> g_tuned;
+thread_local int t_forced_schedule = -1;   // set by the tuner around its timing runs
+
+int tuned_schedule(int device, int prec, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int best = -1;
+    double dist = 0.5;   // |log2(n / n_tuned)|
+    for (const TunedEntry& t : g_tuned) {
+        if (t.device != device || t.prec != prec) continue;
+        const double d = fabs(log2((double)n / (double)t.n));
+        if (d <= dist) {
+            dist = d;
+            best = t.schedule;
+        }
+    }
+    return best;
+}
+
+int use_streamk(int64_t n, const fe_workspace* ws, int prec) {
     if (!ws->sk_partial) return 0;
+    if (t_forced_schedule >= 0) return t_forced_schedule;
     const char* env = getenv("FE_SCHEDULE");
     if (env && env[0] == 'd') return 0;
     if (env && env[0] == 's') return strcmp(env, "sk2") == 0 ? 2 : 1;
+    const int tuned = tuned_schedule(ws->device, prec, n);
+    if (tuned >= 0) return tuned;
     const int64_t np = round_up(n, 128), T = np / 128, ntiles = T * (T + 1) / 2, nk = np / 64;
     const int64_t grid = 2 * (int64_t)ws->n_cu;
     const int64_t rounds = ntiles / grid;
@@ -120,7 +152,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         FE_HIP(fe::launch_small_f64(sa, s));
     } else if (split) {
         fe::SplitPlan plan{};
-        plan.streamk = use_streamk(n, ws);
+        plan.streamk = use_streamk(n, ws, prec);
         plan.grid = plan.streamk == 2 ? 2 * ws->n_cu : ws->n_cu;
         plan.partial = ws->sk_partial;
         plan.own = ws->sk_partial ? ws->sk_partial + (size_t)ws->n_cu * 256 * 256 : nullptr;
@@ -397,6 +429,91 @@ int fe_model_select(const double* H, int64_t n, int64_t ldh, double mu, double k
     FE_HIP(hipMemcpy(&p, ws->params, sizeof(p), hipMemcpyDeviceToHost));
     if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
     *index = choose_bank_model(ms.data(), nbank, p.emin, p.emax, mu, kT);
+    return FE_OK;
+}
+
+int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choice, double* ms,
+                fe_workspace* ws, void* stream) {
+    if (!sizes || count < 1) return fail(FE_ERR_ARG, "no sizes to tune");
+    if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
+        return fail(FE_ERR_ARG, "the tuner chooses among the 16-bit split schedules");
+    int64_t nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        if (sizes[i] < 1) return fail(FE_ERR_ARG, "sizes must be >= 1");
+        nmax = sizes[i] > nmax ? sizes[i] : nmax;
+    }
+    if (nmax > ws->max_n) return fail(FE_ERR_WORKSPACE, "a size exceeds the workspace's max_n");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the timing input: a random symmetric matrix, a short SP2 model (the per-layer cost does not
+    // depend on the coefficients)
+    double* H = nullptr;
+    FE_HIP(hipMalloc(reinterpret_cast<void**>(&H), sizeof(double) * (size_t)nmax * nmax));
+    std::vector<double> theta(4 * 6);
+    fe_sp2_coeffs(0.5, 6, theta.data());
+    fe_model m{6, 100.0, 0.5, theta.data()};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = FE_OK;
+    for (int i = 0; i < count && rc == FE_OK && e == hipSuccess; ++i) {
+        const int64_t n = sizes[i];
+        e = fe::launch_fill_symmetric(H, n, 0x5eedULL + (uint64_t)n, s);
+        const int cands = ws->sk_partial ? 3 : 1;
+        double best = 0.0;
+        int best_s = 0;
+        for (int c = 0; c < 3 && e == hipSuccess && rc == FE_OK; ++c) {
+            if (ms) ms[3 * i + c] = NAN;
+            if (c >= cands) continue;
+            t_forced_schedule = c;
+            float t = 0.0f;
+            for (int rep = 0; rep < 4 && rc == FE_OK && e == hipSuccess; ++rep) {
+                if (rep == 1) e = hipEventRecord(e0, s);   // the first run is a warm-up
+                if (e == hipSuccess)
+                    rc = run_expansion(H, n, n, 0.0, 0.1, &m, prec, 1.0, 0, nullptr, 0, n, nullptr,
+                                       nullptr, nullptr, nullptr, ws, s, 0);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            t_forced_schedule = -1;
+            const double per = t / 3.0;
+            if (ms) ms[3 * i + c] = per;
+            if (c == 0 || per < best) {
+                best = per;
+                best_s = c;
+            }
+        }
+        if (e == hipSuccess && rc == FE_OK) {
+            if (choice) choice[i] = best_s;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            bool found = false;
+            for (TunedEntry& t : g_tuned)
+                if (t.device == ws->device && t.prec == prec && t.n == n) {
+                    t.schedule = best_s;
+                    found = true;
+                }
+            if (!found) g_tuned.push_back({ws->device, prec, n, best_s});
+        }
+    }
+    t_forced_schedule = -1;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(H);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    return rc;
+}
+
+int fe_autotune_lookup(int64_t n, int32_t prec, fe_workspace* ws, int32_t* schedule) {
+    if (!ws || !schedule) return fail(FE_ERR_ARG, "workspace and schedule are required");
+    if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
+    *schedule = use_streamk(n, ws, prec);
+    return FE_OK;
+}
+
+int fe_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
     return FE_OK;
 }
 

@@ -68,6 +68,9 @@ struct RescaleArgs {
     int64_t ldx;
 };
 hipError_t launch_rescale(const RescaleArgs& a, hipStream_t s);
+// A random symmetric n x n matrix (row-major, FP64) for timing runs: diagonal U[-1, 1],
+// off-diagonal U[-1, 1] / sqrt(n), from a hash of (min(i, j), max(i, j), seed).
+hipError_t launch_fill_symmetric(double* H, int64_t n, uint64_t seed, hipStream_t s);
 
 // One layer of the split-precision (FP16x2 / BF16x2) recursion with the fused epilogue.
 struct LayerArgs {

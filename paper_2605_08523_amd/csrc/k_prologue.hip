@@ -231,6 +231,22 @@ k_reduce(const TracePartial* partials, int count, double* out_tr, double* out_sq
     }
 }
 
+__global__ void __launch_bounds__(256) k_fill_symmetric(double* H, int64_t n, uint64_t seed) {
+    const double off = 1.0 / sqrt((double)n);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const uint64_t a = (uint64_t)(i < j ? i : j), b = (uint64_t)(i < j ? j : i);
+        // splitmix64 of the unordered pair and the seed
+        uint64_t z = seed + 0x9e3779b97f4a7c15ULL * (a * 0x100000001b3ULL + b + 1);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+        H[e] = i == j ? u : u * off;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_bounds_params(const double* H, int64_t n, int64_t ldh, double mu, double kT,
@@ -253,6 +269,13 @@ hipError_t launch_rescale(const RescaleArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_rescale<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_rescale<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_symmetric(double* H, int64_t n, uint64_t seed, hipStream_t s) {
+    int64_t blocks = (n * n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_symmetric, dim3((unsigned)blocks), dim3(256), 0, s, H, n, seed);
     return hipGetLastError();
 }
 

@@ -1,0 +1,62 @@
+"""The schedule autotuner (fe_autotune): choices, the process-wide table, and parity of the
+expansion under the tuned schedule."""
+import numpy as np
+import pytest
+
+from oracle import recursion as R
+from paper_2605_08523_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_08523_amd import api as _api
+    _api.lib()
+    yield _api
+    _api.autotune_clear()
+
+
+def test_autotune_table_and_parity(api, paper_model):
+    ws = api.Workspace(4096)
+    api.autotune_clear()
+    default_4096 = api.autotune_lookup(4096, ws=ws)
+    print("case autotune 1024 2048 4096", flush=True)
+    res = api.autotune([1024, 2048, 4096], ws=ws)
+    for r in res:
+        print(f"[autotune] n={r['n']} -> {r['schedule']} ({r['ms']})", flush=True)
+        assert set(r["ms"]) == {"dp128", "sk256", "sk2x128"}
+        assert all(v > 0 for v in r["ms"].values())
+        assert r["ms"][r["schedule"]] == min(r["ms"].values())
+        assert api.autotune_lookup(r["n"], ws=ws) == r["schedule"]
+        assert api.autotune_lookup(int(r["n"] * 1.2), ws=ws) == r["schedule"]
+    # an expansion of a nearby size runs the tuned schedule and stays within the bar
+    m = paper_model
+    H = W.random_dense(1500, 61)
+    Hd = torch.from_numpy(H).cuda()
+    D, _, _, _ = api.expand_density(Hd, 0.1, 0.1, m, ws=ws)
+    torch.cuda.synchronize()
+    Drec, _ = R.mlsp2_density(H, 0.1, 0.1, m.theta, m.beta0, m.mu0)
+    fro = np.linalg.norm(D.double().cpu().numpy() - Drec) / 1500
+    print(f"[autotune] n=1500 under {api.autotune_lookup(1500, ws=ws)}: |dD|_F/N={fro:.3e}", flush=True)
+    assert fro <= 1e-5
+    api.autotune_clear()
+    assert api.autotune_lookup(4096, ws=ws) == default_4096
+    torch.cuda.synchronize()
+    ws.close()
+
+
+def test_autotune_errors(api):
+    ws = api.Workspace(256)
+    with pytest.raises(api.FeError):
+        api.autotune([512], ws=ws)              # beyond the workspace
+    with pytest.raises(api.FeError):
+        api.autotune([128], prec="fp64", ws=ws)
+    res = api.autotune([200], ws=ws)            # small workspace: no stream-K buffers
+    assert res[0]["schedule"] == "dp128" and set(res[0]["ms"]) == {"dp128"}
+    api.autotune_clear()
+    ws.close()
