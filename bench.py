@@ -337,7 +337,7 @@ def main():
 
 def bench_batch(args, torch, api, models, workloads, dev):
     """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (grouped per-layer launches in a
-    hipGraph), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
+    hipGraph; its layer tile, 128 x 128 or 64 x 64, chosen by the plan's autotuner), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
     1e-5 bar on this batch: beta' reaches ~3700). Sampled items are checked against the CPU
     oracle (eigendecomposition) in the cpu_baseline leg."""
     import numpy as np
@@ -348,6 +348,7 @@ def bench_batch(args, torch, api, models, workloads, dev):
     mats = [dict(H=torch.from_numpy(it["H"]).to(dev), mu=it["mu"], kT=it["kT"]) for it in items]
     prec = args.prec
     plan = api.BatchPlan(mats, m, prec=prec)
+    tile, tile_ms = plan.autotune()
     ms = timed(plan.launch, args.steps, args.warmup, torch)
     status = plan.status.cpu().numpy()
     ns = np.array([it["n"] for it in items], dtype=np.float64)
@@ -361,12 +362,14 @@ def bench_batch(args, torch, api, models, workloads, dev):
                       "layers": m.L, "coefficients": "mlsp2_L40_b1e4_mu1third",
                       "precision": prec},
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
-           "status_nonzero": int(np.count_nonzero(status))}
+           "status_nonzero": int(np.count_nonzero(status)),
+           "tile_autotune": {"tile": tile, "ms_per_step": {str(k): v for k, v in tile_ms.items()}}}
     # the same batch over the model bank: each matrix runs the fewest layers valid for it
     bank_names = BANK
     bank = [models.load(x) for x in bank_names]
     plan.close()
     bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)
+    tile_b, tile_ms_b = bplan.autotune()
     ms_b = timed(bplan.launch, args.steps, args.warmup, torch)
     Ls = np.array([bank[k].L for k in bplan.chosen], dtype=np.float64)
     out["model_bank"] = {
@@ -374,7 +377,8 @@ def bench_batch(args, torch, api, models, workloads, dev):
         "models": bank_names,
         "items_per_model": [int(np.sum(bplan.chosen == k)) for k in range(len(bank))],
         "tflops_algorithmic": float(np.sum(Ls * 2.0 * ns ** 3)) / (ms_b * 1e-3) / 1e12,
-        "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy()))}
+        "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy())),
+        "tile_autotune": {"tile": tile_b, "ms_per_step": {str(k): v for k, v in tile_ms_b.items()}}}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         order = np.argsort(ns)

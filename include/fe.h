@@ -209,6 +209,18 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
                               int32_t* status, int32_t* chosen, fe_workspace* ws,
                               fe_batch_plan** plan);
 int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
+
+/* Rebuilds the plan (layout, tables, captured graph) with layer tiles of `tile` x `tile`, tile
+ * 128 (the default: the single-matrix kernel's tiles) or 64 (32 x 32 per wave: less padding for
+ * small matrices, more LDS traffic per flop). Results differ from the other tile size only by the
+ * order of FP32 sums. */
+int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
+
+/* Autotunes the plan's tile size: builds it with each tile size, times three replays of each on
+ * `stream` (after a warm-up), keeps the faster. tile (host, may be NULL) receives the choice, ms
+ * (host, 2 entries, may be NULL) the ms per replay for tiles 128 and 64. Runs the batch 8 times;
+ * synchronizes. */
+int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms);
 int fe_batch_plan_destroy(fe_batch_plan* plan);
 
 /* One-shot batch: create a plan, launch it on `stream`, wait for the stream, destroy the plan. */

@@ -84,6 +84,8 @@ SIGNATURES = {
     "fe_matrix_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
     "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
+    "fe_batch_plan_retile": (_I32, [_P, _I32]),
+    "fe_batch_plan_autotune": (_I32, [_P, _P, C.POINTER(_I32), C.POINTER(_D)]),
     "fe_autotune": (_I32, [C.POINTER(_I64), _I32, _I32, C.POINTER(_I32), C.POINTER(_D), _P, _P]),
     "fe_autotune_lookup": (_I32, [_I64, _I32, _P, C.POINTER(_I32)]),
     "fe_autotune_clear": (_I32, []),
@@ -478,6 +480,17 @@ class BatchPlan:
 
     def launch(self):
         _check(lib().fe_batch_plan_launch(self._p, _stream_ptr()))
+
+    def retile(self, tile: int):
+        """fe_batch_plan_retile: rebuild with 128 x 128 or 64 x 64 layer tiles."""
+        _check(lib().fe_batch_plan_retile(self._p, int(tile)))
+
+    def autotune(self):
+        """fe_batch_plan_autotune: keeps the faster tile size; returns (tile, {tile: ms})."""
+        tile = C.c_int32()
+        ms = (C.c_double * 2)()
+        _check(lib().fe_batch_plan_autotune(self._p, _stream_ptr(), C.byref(tile), ms))
+        return tile.value, {128: ms[0], 64: ms[1]}
 
     def close(self):
         if self._p:

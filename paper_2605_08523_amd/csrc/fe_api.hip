@@ -279,8 +279,9 @@ int fe_workspace_create(int64_t max_n, int32_t max_batch, int64_t batch_elems, f
     if (e == hipSuccess && max_batch > 0) {
         ws->max_batch = max_batch;
         ws->batch_elems = batch_elems;
-        const int64_t bt = fe::batch_tile();
-        ws->batch_tiles = batch_elems / (bt * bt) + max_batch;
+        // tiles of either batch tile size (64: T(T+1)/2 with T = np / 64 <= np^2 / 4096 for
+        // np >= 128, summed over the arena)
+        ws->batch_tiles = batch_elems / 4096 + max_batch;
         e = hipMalloc(&ws->arena, (size_t)batch_elems * 16);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->bmats), (size_t)max_batch * sizeof(fe::BatchMat));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ws->bparams), (size_t)max_batch * sizeof(fe::Params));

@@ -19,10 +19,19 @@ using namespace fehost;
 struct fe_batch_plan {
     uint64_t gen = 0;       // workspace layout generation this plan was built for
     int count = 0;
+    int tile = 128;         // tile size of the layer kernel (128 or 64)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     fe_workspace* ws = nullptr;
     void* tables = nullptr; // device coefficient tables of both passes
+    // what a rebuild with another tile size needs (host copies)
+    std::vector<fe_batch_item> items;
+    std::vector<int> model;
+    std::vector<std::vector<double>> theta;   // density models, then entropy models
+    std::vector<fe_model> dens, ent;
+    double alpha = 1.0;
+    int32_t prec = 0;
+    int32_t* status = nullptr;
 };
 
 namespace {
@@ -86,7 +95,7 @@ PassTables make_tables(const std::vector<const fe_model*>& ms, int prec, double 
 // Enqueues one expansion pass (density or entropy) of the whole batch on `s`. active[l] is the
 // number of tiles of the matrices with more than l layers (a prefix of the sorted batch).
 int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoef& cf,
-                 const std::vector<int>& active, double alpha, int entropy, int bf,
+                 const std::vector<int>& active, double alpha, int entropy, int bf, int tile,
                  int32_t* status, hipStream_t s) {
     if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, s));
     FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, cf, bf, s));
@@ -101,9 +110,10 @@ int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoe
         q.cf = cf;
         q.P = ws->bparams;
         q.partials = ws->btparts;
-        FE_HIP(fe::launch_batch_layer(q, active[l], bf, s));
+        FE_HIP(fe::launch_batch_layer(q, active[l], bf, tile, s));
     }
-    FE_HIP(fe::launch_batch_reduce(ws->bmats, count, ws->btparts, ws->bparams, entropy, status, s));
+    FE_HIP(fe::launch_batch_reduce(ws->bmats, count, ws->btparts, ws->bparams, entropy, status,
+                                   tile, s));
     return FE_OK;
 }
 
@@ -111,8 +121,8 @@ int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoe
 std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<int>& order,
                                  const std::vector<int>& model,
                                  const std::vector<const fe_model*>& ms, fe_workspace* ws,
-                                 int64_t* tiles_out, int64_t* max_np_out) {
-    const int64_t bt = fe::batch_tile();
+                                 int64_t bt, int64_t* tiles_out, int64_t* max_np_out) {
+    const int64_t pad = fe::kBatchPad;
     std::vector<fe::BatchMat> mats(order.size());
     char* arena = static_cast<char*>(ws->arena);
     int64_t off = 0, t0 = 0, max_np = 0;
@@ -120,7 +130,7 @@ std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<i
         const fe_batch_item& it = items[order[k]];
         fe::BatchMat& bm = mats[k];
         memset(&bm, 0, sizeof(bm));
-        const int64_t np = round_up(it.n, bt);
+        const int64_t np = round_up(it.n, pad);
         const size_t e = (size_t)np * np;
         bm.H = it.H;
         bm.n = it.n;
@@ -159,12 +169,12 @@ int check_batch(const fe_batch_item* items, int count, fe_workspace* ws) {
     if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
     if (!items || count < 1) return fail(FE_ERR_ARG, "empty batch");
     if (count > ws->max_batch) return fail(FE_ERR_WORKSPACE, "batch larger than the workspace's max_batch");
-    const int64_t bt = fe::batch_tile();
+    const int64_t bt = 64;   // the larger tile count of the two tile sizes
     int64_t elems = 0, tiles = 0;
     for (int i = 0; i < count; ++i) {
         int rc = check_item(items[i], i);
         if (rc) return rc;
-        const int64_t np = round_up(items[i].n, bt), T = np / bt;
+        const int64_t np = round_up(items[i].n, (int64_t)fe::kBatchPad), T = np / bt;
         elems += np * np;
         tiles += T * (T + 1) / 2;
     }
@@ -174,12 +184,30 @@ int check_batch(const fe_batch_item* items, int count, fe_workspace* ws) {
     return FE_OK;
 }
 
-// Builds and captures a plan: item i runs model dens[model[i]] (and ent[model[i]] for the
-// entropy pass when ent is non-empty).
-int build_plan(const fe_batch_item* items, int count, const std::vector<int>& model,
-               const std::vector<const fe_model*>& dens, const std::vector<const fe_model*>& ent,
-               double alpha, int32_t prec, int32_t* status, fe_workspace* ws,
-               fe_batch_plan** out) {
+// Releases a plan's graph and tables (before a rebuild or on destruction).
+void release_plan(fe_batch_plan* plan) {
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->tables) (void)hipFree(plan->tables);
+    plan->exec = nullptr;
+    plan->graph = nullptr;
+    plan->tables = nullptr;
+}
+
+// Builds and captures `plan` for its stored inputs with layer tiles of `tile` (128 or 64): item i
+// runs model dens[model[i]] (and ent[model[i]] for the entropy pass when ent is non-empty).
+int build_plan(fe_batch_plan* plan, int tile) {
+    release_plan(plan);
+    const fe_batch_item* items = plan->items.data();
+    const int count = plan->count;
+    const std::vector<int>& model = plan->model;
+    std::vector<const fe_model*> dens, ent;
+    for (const fe_model& m : plan->dens) dens.push_back(&m);
+    for (const fe_model& m : plan->ent) ent.push_back(&m);
+    const double alpha = plan->alpha;
+    const int32_t prec = plan->prec;
+    int32_t* status = plan->status;
+    fe_workspace* ws = plan->ws;
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -188,7 +216,8 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
         return items[a].n > items[b].n;
     });
     int64_t tiles = 0, max_np = 0;
-    std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, &tiles, &max_np);
+    std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, tile, &tiles, &max_np);
+    if (tiles > ws->batch_tiles) return fail(FE_ERR_WORKSPACE, "batch has too many tiles for the workspace");
     const PassTables td = make_tables(dens, prec, 1.0);
     PassTables te;
     if (!ent.empty()) te = make_tables(ent, prec, alpha);
@@ -214,9 +243,7 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
         return fail(FE_ERR_ARG, "entropy and density models must order the batch the same way");
     FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
 
-    fe_batch_plan* plan = new fe_batch_plan();
-    plan->count = count;
-    plan->ws = ws;
+    plan->tile = tile;
     // device tables: [density coef | L | d0 | shift0 | entropy ...], 256-byte aligned parts
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t cd = al(td.coef.size() * 4), ld = al(td.L.size() * 4), dd = al(td.d0.size() * 4);
@@ -224,10 +251,7 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
     const size_t ce = al(te.coef.size() * 4), le = al(te.L.size() * 4), de = al(te.d0.size() * 4);
     const size_t se = al(te.shift0.size() * 8);
     hipError_t e = hipMalloc(&plan->tables, cd + ld + dd + sd + ce + le + de + se + 256);
-    if (e != hipSuccess) {
-        delete plan;
-        return hip_fail(e, "hipMalloc (batch tables)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch tables)");
     char* base = static_cast<char*>(plan->tables);
     auto up = [&](size_t off, const void* src, size_t bytes) {
         return bytes ? hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
@@ -248,24 +272,18 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
     if (e == hipSuccess) e = up(eo + ce, te.L.data(), te.L.size() * 4);
     if (e == hipSuccess) e = up(eo + ce + le, te.d0.data(), te.d0.size() * 4);
     if (e == hipSuccess) e = up(eo + ce + le + de, te.shift0.data(), te.shift0.size() * 8);
-    if (e != hipSuccess) {
-        fe_batch_plan_destroy(plan);
-        return hip_fail(e, "hipMemcpy (batch tables)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch tables)");
     plan->gen = ++ws->batch_gen;   // earlier plans on this workspace become stale
     hipStream_t cs;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        fe_batch_plan_destroy(plan);
-        return hip_fail(e, "hipStreamCreate");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
     int rc = FE_OK;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int bf = prec == FE_PREC_BF16X2;
     if (e == hipSuccess) {
-        rc = enqueue_pass(ws, count, max_np, cfd, act_d, 1.0, 0, bf, status, cs);
+        rc = enqueue_pass(ws, count, max_np, cfd, act_d, 1.0, 0, bf, tile, status, cs);
         if (rc == FE_OK && !ent.empty())
-            rc = enqueue_pass(ws, count, max_np, cfe, act_e, alpha, 1, bf, status, cs);
+            rc = enqueue_pass(ws, count, max_np, cfe, act_e, alpha, 1, bf, tile, status, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         plan->graph = g;
@@ -278,6 +296,32 @@ int build_plan(const fe_batch_item* items, int count, const std::vector<int>& mo
         rc = hip_fail(e, "hipStreamBeginCapture");
     }
     (void)hipStreamDestroy(cs);
+    return rc;
+}
+
+// A new plan holding copies of its inputs, built with 128 x 128 layer tiles.
+int create_plan(const fe_batch_item* items, int count, const std::vector<int>& model,
+                const std::vector<const fe_model*>& dens, const std::vector<const fe_model*>& ent,
+                double alpha, int32_t prec, int32_t* status, fe_workspace* ws,
+                fe_batch_plan** out) {
+    fe_batch_plan* plan = new fe_batch_plan();
+    plan->count = count;
+    plan->ws = ws;
+    plan->items.assign(items, items + count);
+    plan->model = model;
+    plan->theta.reserve(dens.size() + ent.size());
+    for (const fe_model* m : dens) {
+        plan->theta.emplace_back(m->theta, m->theta + 4 * m->L);
+        plan->dens.push_back({m->L, m->beta0, m->mu0, plan->theta.back().data()});
+    }
+    for (const fe_model* m : ent) {
+        plan->theta.emplace_back(m->theta, m->theta + 4 * m->L);
+        plan->ent.push_back({m->L, m->beta0, m->mu0, plan->theta.back().data()});
+    }
+    plan->alpha = alpha;
+    plan->prec = prec;
+    plan->status = status;
+    const int rc = build_plan(plan, 128);
     if (rc != FE_OK) {
         fe_batch_plan_destroy(plan);
         return rc;
@@ -319,7 +363,7 @@ int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_mod
     std::vector<int> model(count, 0);
     std::vector<const fe_model*> dens{m}, ent;
     if (mS) ent.push_back(mS);
-    return build_plan(items, count, model, dens, ent, alpha, prec, status, ws, out);
+    return create_plan(items, count, model, dens, ent, alpha, prec, status, ws, out);
 }
 
 int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const fe_model* bank,
@@ -348,7 +392,7 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
     std::vector<int> provisional(count, 0), order(count);
     std::iota(order.begin(), order.end(), 0);
     int64_t tiles = 0, max_np = 0;
-    std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, &tiles, &max_np);
+    std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, 128, &tiles, &max_np);
     FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
     FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, nullptr));
     std::vector<fe::Params> P(count);
@@ -360,7 +404,7 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
     }
     std::vector<const fe_model*> ent;
     if (with_entropy) ent = ms;
-    return build_plan(items, count, model, ms, ent, alpha, prec, status, ws, out);
+    return create_plan(items, count, model, ms, ent, alpha, prec, status, ws, out);
 }
 
 int fe_batch_plan_launch(fe_batch_plan* plan, void* stream) {
@@ -373,11 +417,50 @@ int fe_batch_plan_launch(fe_batch_plan* plan, void* stream) {
 
 int fe_batch_plan_destroy(fe_batch_plan* plan) {
     if (!plan) return FE_OK;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->tables) (void)hipFree(plan->tables);
+    release_plan(plan);
     delete plan;
     return FE_OK;
+}
+
+int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile) {
+    if (!plan) return fail(FE_ERR_ARG, "invalid plan");
+    if (tile != 64 && tile != 128) return fail(FE_ERR_ARG, "tile must be 64 or 128");
+    return build_plan(plan, tile);
+}
+
+int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms) {
+    if (!plan) return fail(FE_ERR_ARG, "invalid plan");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cand[2] = {128, 64};
+    double t_ms[2] = {0.0, 0.0};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FE_HIP(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    int rc = FE_OK;
+    for (int c = 0; c < 2 && rc == FE_OK && e == hipSuccess; ++c) {
+        rc = build_plan(plan, cand[c]);
+        if (rc != FE_OK) break;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {   // one warm-up, three timed
+            if (rep == 1) e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = hipGraphLaunch(plan->exec, s);
+        }
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        t_ms[c] = t / 3.0;
+    }
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    if (rc != FE_OK) return rc;
+    const int best = t_ms[1] < t_ms[0] ? 64 : 128;
+    if (ms) {
+        ms[0] = t_ms[0];
+        ms[1] = t_ms[1];
+    }
+    if (tile) *tile = best;
+    return best == plan->tile ? FE_OK : build_plan(plan, best);
 }
 
 int fe_batched_expand(const fe_batch_item* items, int32_t count, const fe_model* m,

@@ -190,16 +190,18 @@ struct BatchLayerArgs {
     const Params* P;
     TracePartial* partials;
 };
-int batch_tile();
+constexpr int kBatchPad = 128;   // batch matrices are padded to a multiple of this
 // Bounds and rescale parameters of every matrix with its own (beta0, mu0).
 hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s);
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
                                 double alpha, BatchCoef cf, int bf16, hipStream_t s);
 // One layer over the first `active_tiles` tiles of the grouped grid (the matrices whose model
 // has more than q.layer layers come first).
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, hipStream_t s);
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, int tile,
+                              hipStream_t s);   // tile 128 or 64
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
-                               const Params* P, int entropy, int32_t* status, hipStream_t s);
+                               const Params* P, int entropy, int32_t* status, int tile,
+                               hipStream_t s);
 
 // ---- coefficient training --------------------------------------------------------------
 constexpr int kScalarMaxL = 96;

@@ -12,6 +12,7 @@ namespace {
 
 using namespace split;
 using CfgB = Cfg<128, 2, 2, 64, 128, 1>;   // same tile and K loop as the data-parallel single-matrix kernel
+using CfgB64 = Cfg<64, 2, 2, 32, 64, 1>;   // 64 x 64 tiles (32 x 32 per wave): less padding for small N
 
 __device__ inline double wsum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -144,8 +145,9 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
 // One layer for every upper tile of every matrix. Workgroup g finds its matrix by binary search
 // over the tile prefix sums (matrices sorted by decreasing size, so the longest K loops start
 // first), then runs the same K loop and fused epilogue as the single-matrix kernel.
-template <bool BF>
-__global__ void __launch_bounds__(CfgB::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+template <bool BF, class C>
+__global__ void __launch_bounds__(C::NT)
+__attribute__((amdgpu_waves_per_eu(C::BM == 64 ? 4 : 2, C::BM == 64 ? 4 : 2)))
 k_batch_layer(BatchLayerArgs q) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int g = blockIdx.x;
@@ -160,7 +162,7 @@ k_batch_layer(BatchLayerArgs q) {
     if (q.layer >= L) return;   // not launched for such matrices; whole workgroup leaves
     const float* cf = q.cf.coef + ((size_t)m.model * q.cf.max_L + q.layer) * 8;
     const int t = g - m.tile0;
-    const int T = (int)(m.np / CfgB::BM);
+    const int T = (int)(m.np / C::BM);
     int I, J;
     tile_coords(t, T, I, J);
     LayerArgs p;
@@ -185,26 +187,26 @@ k_batch_layer(BatchLayerArgs q) {
     p.out_mode = q.entropy ? 2 : (m.D ? (m.d_is_fp64 ? 1 : 0) : 2);
     p.P = q.P + lo;
     p.partials = q.partials + m.tile0;
-    Acc<CfgB> acc;
+    Acc<C> acc;
 #pragma unroll
-    for (int mb = 0; mb < CfgB::MB; ++mb)
+    for (int mb = 0; mb < C::MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < CfgB::NB; ++nb)
+        for (int nb = 0; nb < C::NB; ++nb)
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc.v[mb][nb][j] = 0.0f;
-    kloop<BF, CfgB>(p.hi_in, p.lo_in, p.np, (int64_t)I * CfgB::BM, (int64_t)J * CfgB::BM, 0,
-                    (int)(p.np / CfgB::BK), acc, reinterpret_cast<uint16_t*>(smem));
-    epilogue<BF, CfgB>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
+    kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
+                    (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
+    epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 
 // Per-matrix fixed-order reduction of the tile traces into Tr, sum of squares, and S (entropy).
 __global__ void __launch_bounds__(64)
 k_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials, const Params* P,
-               int entropy, int32_t* status) {
+               int entropy, int32_t* status, int tile) {
     const int b = blockIdx.x;
     if (b >= count) return;
     const BatchMat m = mats[b];
-    const int T = (int)(m.np / CfgB::BM);
+    const int T = (int)(m.np / tile);
     const int nt = T * (T + 1) / 2;
     double tr = 0.0, sq = 0.0;
     for (int k = threadIdx.x; k < nt; k += 64) {
@@ -245,27 +247,37 @@ hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, hipStream_t s) {
-    static bool done[2] = {false, false};
-    auto kern = bf16 ? k_batch_layer<true> : k_batch_layer<false>;
-    if (!done[bf16]) {
+template <bool BF, class C>
+hipError_t launch_layer_t(const BatchLayerArgs& q, int active_tiles, hipStream_t s) {
+    auto kern = k_batch_layer<BF, C>;
+    static bool done = false;
+    if (!done) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)CfgB::LDS_BYTES);
+                                           (int)C::LDS_BYTES);
         if (e != hipSuccess) return e;
-        done[bf16] = true;
+        done = true;
     }
-    hipLaunchKernelGGL(kern, dim3(active_tiles), dim3(CfgB::NT), CfgB::LDS_BYTES, s, q);
+    hipLaunchKernelGGL(kern, dim3(active_tiles), dim3(C::NT), C::LDS_BYTES, s, q);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, int tile,
+                              hipStream_t s) {
+    if (tile == 64)
+        return bf16 ? launch_layer_t<true, CfgB64>(q, active_tiles, s)
+                    : launch_layer_t<false, CfgB64>(q, active_tiles, s);
+    if (tile != 128) return hipErrorInvalidValue;
+    return bf16 ? launch_layer_t<true, CfgB>(q, active_tiles, s)
+                : launch_layer_t<false, CfgB>(q, active_tiles, s);
 }
 
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
-                               const Params* P, int entropy, int32_t* status, hipStream_t s) {
+                               const Params* P, int entropy, int32_t* status, int tile,
+                               hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reduce, dim3(count), dim3(64), 0, s, mats, count, partials, P,
-                       entropy, status);
+                       entropy, status, tile);
     return hipGetLastError();
 }
-
-int batch_tile() { return CfgB::BM; }
 
 }  // namespace fe

@@ -156,3 +156,45 @@ def test_model_bank_batch(api, monkeypatch):
         fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - ref["D"]) / n
         print(f"[bank item {b}] N={n} kT={it['kT']} model {m.name} |dD|_F/N={fro:.3e}", flush=True)
         assert fro <= 1e-5
+
+
+def test_batch_tile_64_and_autotune(api, paper_model):
+    """64 x 64 layer tiles (fe_batch_plan_retile) against the oracle, and the tile autotuner on a
+    batch of small matrices (N 64 .. 300, where 128-tile padding wastes most)."""
+    m = paper_model
+    rng = np.random.default_rng(91)
+    mats = []
+    for b in range(16):
+        n = int(rng.integers(64, 300))
+        H = W.banded_decay(n, 8.0, 2.0, 700 + b)
+        lam = np.linalg.eigvalsh(H)
+        mu = float(lam[0] + rng.uniform(0.3, 0.7) * (lam[-1] - lam[0]))
+        mats.append(dict(Hn=H, H=torch.from_numpy(H).cuda(), mu=mu, kT=float(rng.uniform(0.05, 0.3))))
+    plan = api.BatchPlan(mats, m, prec="fp16x2", model_s=m, alpha=0.842704)
+    plan.launch()
+    torch.cuda.synchronize()
+    D128 = [d.clone() for d in plan.D]
+    S128 = plan.S.clone()
+    print("case batch16 tile 64", flush=True)
+    plan.retile(64)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert plan.status.cpu().numpy().tolist() == [0] * 16
+    for b, it in enumerate(mats):
+        Drec, _ = R.mlsp2_density(it["Hn"], it["mu"], it["kT"], m.theta, m.beta0, m.mu0)
+        n = Drec.shape[0]
+        fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - Drec) / n
+        d = float((plan.D[b] - D128[b]).abs().max())
+        print(f"[tile64 item {b}] N={n} |dD|_F/N={fro:.3e} max|D64 - D128|={d:.2e}", flush=True)
+        assert fro <= 1e-5 and d < 1e-4
+        assert torch.equal(plan.D[b], plan.D[b].T)
+    assert torch.allclose(plan.S, S128, rtol=1e-5, atol=1e-6)
+    tile, ms = plan.autotune()
+    print(f"[batch autotune] tile {tile} ({ms})", flush=True)
+    assert tile in (64, 128) and ms[tile] == min(ms.values()) and all(v > 0 for v in ms.values())
+    plan.launch()
+    torch.cuda.synchronize()
+    assert plan.status.cpu().numpy().tolist() == [0] * 16
+    for b in range(16):
+        assert float((plan.D[b] - D128[b]).abs().max()) < 1e-4
+    plan.close()
