@@ -164,8 +164,8 @@ def main():
         m = models.load(args.model)
     mref = api.make_model(m.theta, m.beta0, m.mu0)
     m1 = api.make_model(m.theta[-1:], m.beta0, m.mu0)      # one layer: prologue + one layer
-    # tile shape / schedule for this size from the autotuner (recorded for the timed runs)
-    tuned = api.autotune([n], prec=args.prec, ws=ws)[0] if not args.profile else None
+    # tile shape / schedule chosen by the autotuner on this input (recorded for the timed runs)
+    tuned = api.autotune_input(Hd, mu, kT, mref, prec=args.prec, ws=ws) if not args.profile else None
 
     def expand():
         api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws)
@@ -423,6 +423,7 @@ def bench_large(args, torch, api, models, workloads, dev):
     ws = api.Workspace(n)
     D = torch.empty((n, n), dtype=torch.float32, device=dev)
     mref = api.make_model(m.theta, m.beta0, m.mu0)
+    tuned = api.autotune_input(Hd, mu, kT, mref, prec=args.prec, ws=ws)
     _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws,
                                             want_info=True)
     steps = max(1, min(args.steps, 5))
@@ -443,7 +444,9 @@ def bench_large(args, torch, api, models, workloads, dev):
            "dtype": "f16" if args.prec == "fp16x2" else "bf16", "data": "synthetic",
            "config": {"workload": "banded_xi32_N16384_seed4_kT0.02_fill0.4", "N": n,
                       "layers": m.L, "coefficients": "mlsp2_L40_b1e4_mu1third",
-                      "precision": args.prec, "mu": mu, "beta_p": info["beta_p"]},
+                      "precision": args.prec, "mu": mu, "beta_p": info["beta_p"],
+                      "schedule": api.autotune_lookup(n, args.prec, ws)},
+           "autotune": tuned,
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "entropy_ms": ms_s,
            "trD": float(trD), "trD_target": 0.4 * n,
@@ -620,7 +623,8 @@ def bench_sweep(args, torch, api, models, workloads, dev):
         D64 = eig(torch.float64)
         D32 = eig(torch.float32)
         torch.cuda.synchronize()
-        rows.append({"N": n, "ms": ms, "tflops_algorithmic": m.L * 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+        rows.append({"N": n, "ms": ms, "schedule": api.autotune_lookup(n, args.prec, ws),
+                     "tflops_algorithmic": m.L * 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
                      "eigh_fp64_ms": ms64, "eigh_fp32_ms": ms32,
                      "speedup_vs_eigh_fp64": ms64 / ms, "speedup_vs_eigh_fp32": ms32 / ms,
                      "fro_over_N_vs_eigh_fp64": float(torch.linalg.norm(D.double() - D64).item() / n),

@@ -293,7 +293,9 @@ int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_
  * workgroup per CU; 2 = 128 x 128 tiles, stream-K over two workgroups per CU (1 and 2 need a
  * workspace with max_n >= 1536). Each candidate runs a short expansion (1 warm-up + 3 timed, HIP
  * events on the stream) of a device-generated random symmetric matrix of each size; the fastest
- * is recorded process-wide for (device, prec, size). Later expansions of a size within a factor
+ * is recorded process-wide for (device, prec, size). The timing model is a 6-layer SP2 recursion
+ * with a small accumulator weight on every layer (the accumulator epilogue runs every second
+ * layer, as in trained models). Later expansions of a size within a factor
  * sqrt(2) of a tuned one use its schedule (FE_SCHEDULE still overrides). sizes: host, count
  * entries, each <= ws max_n. choice (host, count, may be NULL) receives the chosen schedules, ms
  * (host, 3 x count, may be NULL) each candidate's time per expansion (NaN if not run). prec:
@@ -301,6 +303,17 @@ int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_
  * synchronizes. */
 int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choice, double* ms,
                 fe_workspace* ws, void* stream);
+
+/* The same choice made on the caller's own input: each candidate runs the expansion of H (n x n,
+ * leading dimension ldh, device FP64) at (mu, kT) with model m (1 warm-up + 2 timed), and the
+ * fastest is recorded for (device, prec, n) as above. The layer kernel's MFMA rate depends on the
+ * data (a banded H runs its layers 20-26% faster than a random dense one of the same size, and
+ * not equally under every schedule), so this is the tuner to use when the inputs of a run look
+ * alike. choice: host, may be NULL. ms: host, 3 entries, may be NULL (NaN where not run).
+ * Arguments are checked as for fe_expand_density; allocates nothing; synchronizes. */
+int fe_autotune_input(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* m, int32_t prec, int32_t* choice, double* ms,
+                      fe_workspace* ws, void* stream);
 
 /* The schedule an expansion of size n with precision prec on ws would use now (host out). */
 int fe_autotune_lookup(int64_t n, int32_t prec, fe_workspace* ws, int32_t* schedule);

@@ -87,6 +87,8 @@ SIGNATURES = {
     "fe_batch_plan_retile": (_I32, [_P, _I32]),
     "fe_batch_plan_autotune": (_I32, [_P, _P, C.POINTER(_I32), C.POINTER(_D)]),
     "fe_autotune": (_I32, [C.POINTER(_I64), _I32, _I32, C.POINTER(_I32), C.POINTER(_D), _P, _P]),
+    "fe_autotune_input": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, C.POINTER(_I32),
+                                 C.POINTER(_D), _P, _P]),
     "fe_autotune_lookup": (_I32, [_I64, _I32, _P, C.POINTER(_I32)]),
     "fe_autotune_clear": (_I32, []),
     "fe_qmodel_coef_count": (_I32, [_I32, _I32, _I32, _I32, C.POINTER(_I64)]),
@@ -307,6 +309,21 @@ def autotune(sizes, prec: str = "fp16x2", ws: Workspace | None = None):
     return [{"n": n, "schedule": SCHEDULES[choice[i]],
              "ms": {SCHEDULES[c]: ms[3 * i + c] for c in range(3) if ms[3 * i + c] == ms[3 * i + c]}}
             for i, n in enumerate(sizes)]
+
+
+def autotune_input(H, mu: float, kT: float, model, prec: str = "fp16x2",
+                   ws: Workspace | None = None):
+    """fe_autotune_input: the schedule choice made on this input; returns {n, schedule, ms}."""
+    n, ldh = _check_H(H)
+    ws = ws or workspace(n)
+    ref = _model_of(model)
+    choice = C.c_int32()
+    ms = (C.c_double * 3)()
+    _check(lib().fe_autotune_input(C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT),
+                                   C.byref(ref.struct), PREC[prec], C.byref(choice), ms, ws.handle,
+                                   _stream_ptr()))
+    return {"n": n, "schedule": SCHEDULES[choice.value],
+            "ms": {SCHEDULES[c]: ms[c] for c in range(3) if ms[c] == ms[c]}}
 
 
 def autotune_lookup(n: int, prec: str = "fp16x2", ws: Workspace | None = None) -> str:

@@ -433,6 +433,77 @@ int fe_model_select(const double* H, int64_t n, int64_t ldh, double mu, double k
     return FE_OK;
 }
 
+namespace {
+
+// Times each schedule candidate on one expansion of H (1 warm-up + reps timed, HIP events on s),
+// writes ms3[c] (NaN for candidates not run) and records the fastest for (device, prec, n).
+int time_schedules(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
+                   int32_t prec, int reps, double* ms3, int* best_out, fe_workspace* ws,
+                   hipStream_t s) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = FE_OK;
+    const int cands = ws->sk_partial ? 3 : 1;
+    double best = 0.0;
+    int best_s = 0;
+    for (int c = 0; c < 3 && e == hipSuccess && rc == FE_OK; ++c) {
+        if (ms3) ms3[c] = NAN;
+        if (c >= cands) continue;
+        t_forced_schedule = c;
+        float t = 0.0f;
+        for (int rep = 0; rep <= reps && rc == FE_OK && e == hipSuccess; ++rep) {
+            if (rep == 1) e = hipEventRecord(e0, s);   // the first run is a warm-up
+            if (e == hipSuccess)
+                rc = run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, nullptr, 0, n, nullptr,
+                                   nullptr, nullptr, nullptr, ws, s, 0);
+        }
+        if (e == hipSuccess && rc == FE_OK) e = hipEventRecord(e1, s);
+        if (e == hipSuccess && rc == FE_OK) e = hipEventSynchronize(e1);
+        if (e == hipSuccess && rc == FE_OK) e = hipEventElapsedTime(&t, e0, e1);
+        t_forced_schedule = -1;
+        if (e != hipSuccess || rc != FE_OK) break;
+        const double per = t / reps;
+        if (ms3) ms3[c] = per;
+        if (c == 0 || per < best) {
+            best = per;
+            best_s = c;
+        }
+    }
+    t_forced_schedule = -1;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (rc != FE_OK) return rc;
+    if (best_out) *best_out = best_s;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TunedEntry& t : g_tuned)
+        if (t.device == ws->device && t.prec == prec && t.n == n) {
+            t.schedule = best_s;
+            return FE_OK;
+        }
+    g_tuned.push_back({ws->device, prec, n, best_s});
+    return FE_OK;
+}
+
+}  // namespace
+
+int fe_autotune_input(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                      const fe_model* m, int32_t prec, int32_t* choice, double* ms,
+                      fe_workspace* ws, void* stream) {
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
+        return fail(FE_ERR_ARG, "the tuner chooses among the 16-bit split schedules");
+    int rc = check_common(H, n, ldh, mu, kT, ws);
+    if (rc) return rc;
+    rc = check_model(m, "model");
+    if (rc) return rc;
+    int best = 0;
+    rc = time_schedules(H, n, ldh, mu, kT, m, prec, 2, ms, &best, ws,
+                        static_cast<hipStream_t>(stream));
+    if (rc == FE_OK && choice) *choice = best;
+    return rc;
+}
+
 int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choice, double* ms,
                 fe_workspace* ws, void* stream) {
     if (!sizes || count < 1) return fail(FE_ERR_ARG, "no sizes to tune");
@@ -446,60 +517,25 @@ int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choi
     }
     if (nmax > ws->max_n) return fail(FE_ERR_WORKSPACE, "a size exceeds the workspace's max_n");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // the timing input: a random symmetric matrix, a short SP2 model (the per-layer cost does not
-    // depend on the coefficients)
+    // the timing input: a random symmetric matrix and a short SP2 model with a small accumulator
+    // weight on every layer, so that the accumulator is updated on every second layer as in the
+    // trained models (those epilogues read and write A: they cost more than the others)
     double* H = nullptr;
     FE_HIP(hipMalloc(reinterpret_cast<void**>(&H), sizeof(double) * (size_t)nmax * nmax));
     std::vector<double> theta(4 * 6);
     fe_sp2_coeffs(0.5, 6, theta.data());
+    for (int l = 0; l < 6; ++l) theta[4 * l + 3] = 1e-3;
     fe_model m{6, 100.0, 0.5, theta.data()};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
     int rc = FE_OK;
-    for (int i = 0; i < count && rc == FE_OK && e == hipSuccess; ++i) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < count && rc == FE_OK; ++i) {
         const int64_t n = sizes[i];
         e = fe::launch_fill_symmetric(H, n, 0x5eedULL + (uint64_t)n, s);
-        const int cands = ws->sk_partial ? 3 : 1;
-        double best = 0.0;
-        int best_s = 0;
-        for (int c = 0; c < 3 && e == hipSuccess && rc == FE_OK; ++c) {
-            if (ms) ms[3 * i + c] = NAN;
-            if (c >= cands) continue;
-            t_forced_schedule = c;
-            float t = 0.0f;
-            for (int rep = 0; rep < 4 && rc == FE_OK && e == hipSuccess; ++rep) {
-                if (rep == 1) e = hipEventRecord(e0, s);   // the first run is a warm-up
-                if (e == hipSuccess)
-                    rc = run_expansion(H, n, n, 0.0, 0.1, &m, prec, 1.0, 0, nullptr, 0, n, nullptr,
-                                       nullptr, nullptr, nullptr, ws, s, 0);
-            }
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            t_forced_schedule = -1;
-            const double per = t / 3.0;
-            if (ms) ms[3 * i + c] = per;
-            if (c == 0 || per < best) {
-                best = per;
-                best_s = c;
-            }
-        }
-        if (e == hipSuccess && rc == FE_OK) {
-            if (choice) choice[i] = best_s;
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            bool found = false;
-            for (TunedEntry& t : g_tuned)
-                if (t.device == ws->device && t.prec == prec && t.n == n) {
-                    t.schedule = best_s;
-                    found = true;
-                }
-            if (!found) g_tuned.push_back({ws->device, prec, n, best_s});
-        }
+        if (e != hipSuccess) break;
+        int best = 0;
+        rc = time_schedules(H, n, n, 0.0, 0.1, &m, prec, 3, ms ? ms + 3 * i : nullptr, &best, ws, s);
+        if (rc == FE_OK && choice) choice[i] = best;
     }
-    t_forced_schedule = -1;
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(H);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     return rc;

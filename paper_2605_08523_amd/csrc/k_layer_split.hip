@@ -20,7 +20,8 @@
 //        inside a tile publishes its FP32 partial; the workgroup that finishes the tile adds the
 //        earlier workgroups' partials in a fixed order in its epilogue (accumulators stay in
 //        registers);
-//      stream-K over 256 x 256 tiles (eight 128 x 64 wave tiles, double-buffered LDS), one
+//      stream-K over 256 x 256 tiles (eight 128 x 64 wave tiles, two LDS stages filled by
+//        direct global-to-LDS loads, fragment reads interleaved with the MFMAs), one
 //        workgroup per CU: the same, with every segment's accumulators staged through memory
 //        right after its K loop (128 per lane would not survive the epilogue in registers).
 //    A workgroup only ever waits for workgroups with smaller ids, which were dispatched earlier,
@@ -33,7 +34,7 @@ namespace {
 using namespace split;
 
 using CfgDP = Cfg<128, 2, 2, 64, 128, 1>;
-using CfgSK = Cfg<256, 2, 4, 32, 128, 2>;
+using CfgSK = Cfg<256, 2, 4, 32, 128, 2, 1>;   // direct-to-LDS operand staging
 using CfgSK2 = Cfg<128, 2, 2, 64, 128, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
 
 constexpr int kSpinLimit = 1 << 22;   // ~0.2 s of s_sleep before a wait gives up

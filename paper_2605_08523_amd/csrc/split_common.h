@@ -113,12 +113,14 @@ __device__ inline int xcd_tile(int b, int ntiles) {
     return b < 8 * per ? (b % 8) * per + b / 8 : b;
 }
 
-// Compile-time shape of one kernel configuration.
-template <int BM_, int WM_, int WN_, int BK_, int EC_, int STAGES_>
+// Compile-time shape of one kernel configuration. DMA = 1: operands go from global memory straight
+// to LDS (no register staging), in unpadded rows whose 16-byte chunks are XOR-swizzled.
+template <int BM_, int WM_, int WN_, int BK_, int EC_, int STAGES_, int DMA_ = 0>
 struct Cfg {
     static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_, EC = EC_, STAGES = STAGES_;
+    static constexpr int DMA = DMA_;
     static constexpr int NT = WM * WN * 64;
-    static constexpr int LDK = BK + 8;                // padded LDS row (16-bit elements)
+    static constexpr int LDK = DMA ? BK : BK + 8;     // LDS row (16-bit elements)
     static constexpr int WAVE_M = BM / WM, WAVE_N = BM / WN;
     static constexpr int MB = WAVE_M / 32, NB = WAVE_N / 32;
     static constexpr int CPR = BK / 8;                // 16-byte chunks per panel row
@@ -132,20 +134,159 @@ struct Cfg {
     static_assert(WAVE_M % 32 == 0 && WAVE_N % 32 == 0, "wave tile");
     static_assert(BM % EC == 0 && EC % 32 == 0 && (EC * BM) % NT == 0, "epilogue chunk");
     static_assert(EC % 16 == 0 && LDY % 4 == 0, "vectorised epilogue");
+    static_assert(!DMA || (STAGES == 2 && BK >= 16 && BK <= 64 && (4 * BM * BK / 512) % (NT / 64) == 0),
+                  "direct-to-LDS staging");
 };
+
+// N groups of (two MFMAs, one LDS read) for the scheduler.
+template <int N>
+__device__ inline void sgb_interleave() {
+    if constexpr (N > 0) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        sgb_interleave<N - 1>();
+    }
+}
 
 template <class C>
 struct Acc {
     floatx16 v[C::MB][C::NB];
 };
 
+// Direct-to-LDS form of the K loop (C::DMA): each lane's global_load_lds_dwordx4 moves one
+// 16-byte chunk, and the 64 chunks of one instruction land in 1 KiB of LDS in lane order. A stage
+// holds the four BM x BK operand panels (A hi, A lo, B hi, B lo) in unpadded rows; chunk c of row
+// r sits at position c ^ ((r / RP) % CPR) of its row (RP rows per 128 bytes), so the eight rows
+// that a quarter-wave's fragment read touches fall on distinct banks. Two stages: block kb + 1
+// is in flight while block kb is multiplied. The barrier is a bare s_barrier after an explicit
+// wait for this wave's own loads (a full __syncthreads would also drain everything else in
+// flight); the fragment reads of the next K step are interleaved with the current step's MFMAs.
+template <bool BF, class C>
+__device__ inline void kloop_dma(const uint16_t* __restrict__ hin, const uint16_t* __restrict__ lin,
+                                 int64_t np, int64_t I0, int64_t J0, int kb0, int kb1, Acc<C>& acc,
+                                 uint16_t* smem) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef const __attribute__((address_space(1))) void global_void;
+    constexpr int CPR = C::BK / 8, RP = 8 / CPR > 0 ? 8 / CPR : 1, RPI = 64 / CPR;
+    constexpr int IPA = C::BM / RPI;                      // 1-KiB instructions per panel and stage
+    constexpr int NW = C::NT / 64, IPW = 4 * IPA / NW;    // per wave and stage
+    constexpr int PANEL = C::BM * C::BK, STAGE = 4 * PANEL;
+    static_assert((RPI / RP) % CPR == 0, "a lane's chunk position is the same in every instruction");
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    auto swz = [](int r, int c) { return c ^ ((r / RP) % CPR); };
+    // Instruction q of this wave covers panel a, rows blk * RPI .. + RPI - 1: a wave-uniform base
+    // (scalar registers) plus the lane's offset, the same for every q.
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const uint32_t lane_off = (uint32_t)((lane / CPR) * np + swz(lane / CPR, lane % CPR) * 8);
+    const uint16_t* src[IPW];
+    int dst[IPW];
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) {
+        const int gi = wave_u + q * NW, a = gi / IPA, blk = gi % IPA;
+        src[q] = ((a & 1) ? lin : hin) + ((a < 2 ? I0 : J0) + blk * RPI) * np;
+        dst[q] = a * PANEL + blk * RPI * C::BK;
+    }
+    auto issue = [&](int kb, uint16_t* stage) {
+        const int64_t k0 = (int64_t)kb * C::BK;
+#pragma unroll
+        for (int q = 0; q < IPW; ++q)
+            __builtin_amdgcn_global_load_lds((global_void*)(src[q] + k0 + lane_off),
+                                             (lds_void*)(stage + dst[q]), 16, 0, 0);
+    };
+    const int frag_row = lane & 31, frag_c = lane >> 5;
+    struct Frag {
+        u32x4 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+    };
+    auto ld = [&](const uint16_t* stage, int ks, Frag& f) {
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) {
+            const int r = wm * C::WAVE_M + mb * 32 + frag_row;
+            const int o = r * C::BK + swz(r, ks * 2 + frag_c) * 8;
+            f.ah[mb] = *reinterpret_cast<const u32x4*>(stage + o);
+            f.al[mb] = *reinterpret_cast<const u32x4*>(stage + PANEL + o);
+        }
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+            const int r = wn * C::WAVE_N + nb * 32 + frag_row;
+            const int o = r * C::BK + swz(r, ks * 2 + frag_c) * 8;
+            f.bh[nb] = *reinterpret_cast<const u32x4*>(stage + 2 * PANEL + o);
+            f.bl[nb] = *reinterpret_cast<const u32x4*>(stage + 3 * PANEL + o);
+        }
+    };
+    auto mm = [&](const Frag& f) {
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) {
+            const u32x4 ahs = scale_hi<BF>(f.ah[mb]);
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb)
+                acc.v[mb][nb] = mfma3<BF>(ahs, f.ah[mb], f.al[mb], f.bh[nb], f.bl[nb], acc.v[mb][nb]);
+        }
+    };
+    // Scheduling of one step: the hi scaling first, then each fragment read of the next step
+    // between MFMAs of this one.
+    constexpr int NDS = 2 * (C::MB + C::NB), NMF = 3 * C::MB * C::NB;
+    static_assert(NMF >= 2 * NDS, "interleave pattern");
+    auto pattern = [&](bool reads) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 4 * C::MB, 0);
+        if (reads) {
+            sgb_interleave<NDS>();
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF - 2 * NDS, 0);
+        } else {
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    constexpr int KS = C::BK / 16;
+    static_assert(KS % 2 == 0, "two fragment sets");
+    auto compute = [&](const uint16_t* stage) {
+        Frag f0, f1;
+        ld(stage, 0, f0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < KS; ks += 2) {
+            ld(stage, ks + 1, f1);
+            mm(f0);
+            pattern(true);
+            if (ks + 2 < KS) {
+                ld(stage, ks + 2, f0);
+                mm(f1);
+                pattern(true);
+            } else {
+                mm(f1);
+                pattern(false);
+            }
+        }
+    };
+    if (kb0 < kb1) issue(kb0, smem);
+    for (int kb = kb0; kb < kb1; ++kb) {
+        uint16_t* cur = smem + ((kb - kb0) & 1) * STAGE;
+        uint16_t* nxt = smem + (((kb - kb0) & 1) ^ 1) * STAGE;
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's chunks of block kb landed
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();          // ... and every wave's; nxt is no longer read
+        asm volatile("" ::: "memory");
+        if (kb + 1 < kb1) issue(kb + 1, nxt);
+        compute(cur);
+    }
+    asm volatile("" ::: "memory");
+    __syncthreads();
+}
+
 // acc += s * (rows I0..I0+BM) (rows J0..J0+BM)^T over K blocks [kb0, kb1) of the current layer's
 // hi/lo operands. STAGES = 1: single LDS buffer with register prefetch (two barriers per block);
-// STAGES = 2: double-buffered LDS (one barrier per block).
+// STAGES = 2: double-buffered LDS (one barrier per block); DMA: see kloop_dma. Ends with a
+// barrier.
 template <bool BF, class C>
 __device__ inline void kloop(const uint16_t* __restrict__ hin, const uint16_t* __restrict__ lin,
                              int64_t np, int64_t I0, int64_t J0, int kb0, int kb1, Acc<C>& acc,
                              uint16_t* smem) {
+    if constexpr (C::DMA) {
+        kloop_dma<BF, C>(hin, lin, np, I0, J0, kb0, kb1, acc, smem);
+        return;
+    }
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));   // keep address arithmetic inside a caller's persistent loop
     const int lane = tid & 63, wave = tid >> 6;

@@ -60,3 +60,41 @@ def test_autotune_errors(api):
     assert res[0]["schedule"] == "dp128" and set(res[0]["ms"]) == {"dp128"}
     api.autotune_clear()
     ws.close()
+
+
+def test_autotune_on_input(api, paper_model, monkeypatch):
+    """fe_autotune_input times the schedules on the caller's own expansion: the choice is the
+    fastest candidate, is recorded for the size, and the expansion under it is bitwise the one
+    that schedule gives when forced, within the bar of the oracle's FP64 recursion."""
+    m = paper_model
+    n = 1700
+    H = W.banded_decay(n, 8.0, 2.0, 62)
+    Hd = torch.from_numpy(H).cuda()
+    mu, kT = 0.1, 0.1
+    ws = api.Workspace(2048)
+    api.autotune_clear()
+    print(f"case autotune_input banded{n}", flush=True)
+    r = api.autotune_input(Hd, mu, kT, m, ws=ws)
+    print(f"[autotune_input] n={n} -> {r['schedule']} ({r['ms']})", flush=True)
+    assert r["n"] == n and set(r["ms"]) == {"dp128", "sk256", "sk2x128"}
+    assert r["ms"][r["schedule"]] == min(r["ms"].values())
+    assert api.autotune_lookup(n, ws=ws) == r["schedule"]
+    D = api.expand_density(Hd, mu, kT, m, ws=ws)[0].cpu().numpy()
+    forced = {"dp128": "dp", "sk256": "sk", "sk2x128": "sk2"}[r["schedule"]]
+    monkeypatch.setenv("FE_SCHEDULE", forced)
+    Df = api.expand_density(Hd, mu, kT, m, ws=ws)[0].cpu().numpy()
+    monkeypatch.delenv("FE_SCHEDULE")
+    assert np.array_equal(D, Df)
+    Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
+    fro = np.linalg.norm(D - Drec) / n
+    print(f"[autotune_input] |dD|_F/N={fro:.3e}", flush=True)
+    assert fro <= 1e-5
+    # argument checks as for the expansion: no timing runs, no table entry
+    api.autotune_clear()
+    with pytest.raises(api.FeError):
+        api.autotune_input(Hd, mu, -1.0, m, ws=ws)
+    with pytest.raises(api.FeError):
+        api.autotune_input(Hd, mu, kT, m, prec="fp32", ws=ws)
+    api.autotune_clear()
+    torch.cuda.synchronize()
+    ws.close()
