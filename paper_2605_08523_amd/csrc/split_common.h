@@ -138,13 +138,13 @@ struct Cfg {
                   "direct-to-LDS staging");
 };
 
-// N groups of (two MFMAs, one LDS read) for the scheduler.
-template <int N>
+// N groups of (M MFMAs, one LDS read) for the scheduler.
+template <int N, int M>
 __device__ inline void sgb_interleave() {
     if constexpr (N > 0) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, M, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        sgb_interleave<N - 1>();
+        sgb_interleave<N - 1, M>();
     }
 }
 
@@ -228,12 +228,13 @@ __device__ inline void kloop_dma(const uint16_t* __restrict__ hin, const uint16_
     // Scheduling of one step: the hi scaling first, then each fragment read of the next step
     // between MFMAs of this one.
     constexpr int NDS = 2 * (C::MB + C::NB), NMF = 3 * C::MB * C::NB;
-    static_assert(NMF >= 2 * NDS, "interleave pattern");
+    constexpr int PER = NMF >= 2 * NDS ? 2 : 1;   // MFMAs between two fragment reads
+    static_assert(NMF >= PER * NDS, "interleave pattern");
     auto pattern = [&](bool reads) {
         __builtin_amdgcn_sched_group_barrier(0x002, 4 * C::MB, 0);
         if (reads) {
-            sgb_interleave<NDS>();
-            __builtin_amdgcn_sched_group_barrier(0x008, NMF - 2 * NDS, 0);
+            sgb_interleave<NDS, PER>();
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF - PER * NDS, 0);
         } else {
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
         }
