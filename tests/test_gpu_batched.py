@@ -107,6 +107,9 @@ def test_batch_config_family(api):
 
 BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
         "mlsp2_L40_b1e4_mu1third"]
+# both trained families: mu0 = 1/3 and mu0 = 1/2 (regions of validity that meet at mu' = 0.4)
+BANK_MIXED = BANK + ["mlsp2_L20_b300_mu0p5", "mlsp2_L22_b600_mu0p5", "mlsp2_L24_b1500_mu0p5",
+                     "mlsp2_L36_b1e4_mu0p5"]
 
 
 def expected_choice(H, mu, kT, bank):
@@ -121,9 +124,11 @@ def expected_choice(H, mu, kT, bank):
     return min(fits, key=lambda k: (bank[k].L, -bank[k].beta0))
 
 
-def test_model_bank_batch(api, monkeypatch):
+@pytest.mark.parametrize("bank_name", ["mu1third", "mixed"])
+def test_model_bank_batch(api, monkeypatch, bank_name):
     from paper_2605_08523_amd import models
-    bank = [models.load(x) for x in BANK]
+    names = BANK if bank_name == "mu1third" else BANK_MIXED
+    bank = [models.load(x) for x in names]
     rng = np.random.default_rng(77)
     mats = []
     for b in range(10):
@@ -133,7 +138,7 @@ def test_model_bank_batch(api, monkeypatch):
         mu = float(lam[0] + rng.uniform(0.3, 0.7) * (lam[-1] - lam[0]))
         kT = float([0.3, 0.12, 0.05, 0.02, 0.01][b % 5])
         mats.append(dict(Hn=H, H=torch.from_numpy(H).cuda(), mu=mu, kT=kT))
-    print("case model-bank batch10 fp16x2", flush=True)
+    print(f"case model-bank batch10 fp16x2 bank {bank_name}", flush=True)
     plan = api.BatchPlan(mats, bank, prec="fp16x2", with_entropy=True, alpha=0.842704)
     plan.launch()
     torch.cuda.synchronize()
@@ -142,6 +147,8 @@ def test_model_bank_batch(api, monkeypatch):
     print("[bank] chosen", plan.chosen.tolist(), "expected", want, flush=True)
     assert plan.chosen.tolist() == want
     assert len(set(want)) >= 3          # the batch really mixes models
+    if bank_name == "mixed":
+        assert any(bank[k].mu0 == 0.5 for k in want) and any(bank[k].mu0 != 0.5 for k in want)
     monkeypatch.setenv("FE_SCHEDULE", "dp")
     for b, it in enumerate(mats):
         m = bank[int(plan.chosen[b])]
