@@ -411,7 +411,8 @@ def bench_large(args, torch, api, models, workloads, dev):
     filling), the 40-layer (1e4, 1/3) model: density (FP16x2) and entropy (FP16x2, theta_fermi
     reused, alpha = 0.842704). mu is the midpoint of eigenvalues 0.4N and 0.4N + 1 (GPU
     eigvalsh; input generation). Checked against the FP64 expansion on the GPU (the oracle's
-    eigendecomposition would take tens of minutes at this size)."""
+    eigendecomposition would take tens of minutes at this size). Also timed with the model the
+    bank selects for the matrix (`model_bank`)."""
     import numpy as np
     m = models.load("mlsp2_L40_b1e4_mu1third")
     t0 = time.perf_counter()
@@ -440,6 +441,20 @@ def bench_large(args, torch, api, models, workloads, dev):
     S64 = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec="fp64", ws=ws)[0])
     torch.cuda.synchronize()
     err = (D.double() - D64)
+    # the same solve with the model the bank selects for this matrix (selection inside the step)
+    bank = [models.load(x) for x in BANK]
+    bank_refs = [api.make_model(x.theta, x.beta0, x.mu0) for x in bank]
+    kb = api.select_model(Hd, mu, kT, bank_refs, ws=ws)
+
+    def bank_step():
+        k = api.select_model(Hd, mu, kT, bank_refs, ws=ws)
+        api.expand_density(Hd, mu, kT, bank_refs[k], prec=args.prec, out=D, ws=ws)
+    ms_b = timed(bank_step, steps, 1, torch)
+    Db64 = api.expand_density(Hd, mu, kT, bank_refs[kb], prec="fp64", ws=ws,
+                              out_dtype=torch.float64)[0]
+    torch.cuda.synchronize()
+    bank_err = float(torch.linalg.norm(D.double() - Db64).item() / n)
+    del Db64
     flop = m.L * 2.0 * n ** 3
     out = {"metric": "density matrices/s (single N = 16384 solve)",
            "value": 1000.0 / ms, "unit": "density matrices/s", "n_gpus": 1, "steps": steps,
@@ -456,7 +471,11 @@ def bench_large(args, torch, api, models, workloads, dev):
            "vs_fp64_expansion": {"fro_over_N": float(torch.linalg.norm(err).item() / n),
                                  "max_abs": float(err.abs().max().item()),
                                  "abs_dTrD": abs(float(trD) - float(trD64)),
-                                 "abs_dS": abs(S - S64), "S": S}}
+                                 "abs_dS": abs(S - S64), "S": S},
+           "model_bank": {"model": BANK[kb], "layers": bank[kb].L, "ms_per_step": ms_b,
+                          "value": 1000.0 / ms_b,
+                          "what": "model selection (bounds pass + read-back) + density expansion",
+                          "fro_over_N_vs_fp64_expansion": bank_err}}
     print(json.dumps(out), flush=True)
 
 
