@@ -32,8 +32,9 @@ HBM_GBS = 8000.0
 # The model bank: two trained families, mu0 = 1/3 and mu0 = 1/2 (each matrix runs the fewest
 # layers whose region of validity holds its (beta', mu'))
 BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
-        "mlsp2_L40_b1e4_mu1third", "mlsp2_L20_b300_mu0p5", "mlsp2_L22_b600_mu0p5",
-        "mlsp2_L24_b1500_mu0p5", "mlsp2_L36_b1e4_mu0p5"]
+        "mlsp2_L40_b1e4_mu1third", "mlsp2_L18_b150_mu0p5", "mlsp2_L19_b200_mu0p5",
+        "mlsp2_L20_b300_mu0p5", "mlsp2_L22_b600_mu0p5", "mlsp2_L24_b1500_mu0p5",
+        "mlsp2_L36_b1e4_mu0p5"]
 
 
 def parse():
