@@ -447,9 +447,9 @@ int time_schedules(const double* H, int64_t n, int64_t ldh, double mu, double kT
     const int cands = ws->sk_partial ? 3 : 1;
     double best = 0.0;
     int best_s = 0;
-    for (int c = 0; c < 3 && e == hipSuccess && rc == FE_OK; ++c) {
-        if (ms3) ms3[c] = NAN;
-        if (c >= cands) continue;
+    if (ms3)
+        for (int c = 0; c < 3; ++c) ms3[c] = NAN;
+    for (int c = 0; c < cands && e == hipSuccess && rc == FE_OK; ++c) {
         t_forced_schedule = c;
         float t = 0.0f;
         for (int rep = 0; rep <= reps && rc == FE_OK && e == hipSuccess; ++rep) {
