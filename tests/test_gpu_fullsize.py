@@ -52,7 +52,9 @@ def test_batch1024_sampled_against_oracle(api):
         assert np.array_equal(Dg, Dg.T)
 
 
-def test_large16384_against_fp64_expansion(api):
+def test_large16384_against_fp64_expansion(api, monkeypatch):
+    """Every schedule (the data-parallel one the bench's input tuner picks for this matrix, the
+    two stream-K ones) against one FP64 expansion."""
     m = models.load("mlsp2_L40_b1e4_mu1third")
     c = W.config_large_banded()
     n = c["H"].shape[0]
@@ -63,20 +65,25 @@ def test_large16384_against_fp64_expansion(api):
     mu, kT = float(0.5 * (lam[k - 1] + lam[k])), c["kT"]
     print(f"case large16384 mu={mu:.6f}", flush=True)
     ws = api.Workspace(n)
-    D, tr, tr2, info = api.expand_density(Hd, mu, kT, m, prec="fp16x2", ws=ws, want_info=True)
-    torch.cuda.synchronize()
-    assert info["clamped"] == 0
-    assert torch.equal(D, D.T)
     D64, tr64, _, _ = api.expand_density(Hd, mu, kT, m, prec="fp64", ws=ws,
                                          out_dtype=torch.float64, want_info=True)
     torch.cuda.synchronize()
-    err = D.double() - D64
-    fro = float(torch.linalg.norm(err).item()) / n
-    print(f"[large16384] |dD|_F/N={fro:.3e} max={float(err.abs().max()):.3e} TrD={float(tr):.4f} "
-          f"(target {0.4 * n}) TrD64={float(tr64):.4f}", flush=True)
-    assert fro <= 1e-5
-    assert 0.0 <= float(tr2) <= float(tr) + 1e-6 * n
-    assert abs(float(tr) - 0.4 * n) < 0.01 * n
-    del D64, err
+    for sch in ("dp", "sk2", "sk"):
+        monkeypatch.setenv("FE_SCHEDULE", sch)
+        print(f"case large16384 schedule {sch}", flush=True)
+        D, tr, tr2, info = api.expand_density(Hd, mu, kT, m, prec="fp16x2", ws=ws, want_info=True)
+        torch.cuda.synchronize()
+        assert info["clamped"] == 0
+        assert torch.equal(D, D.T)
+        err = D.double() - D64
+        fro = float(torch.linalg.norm(err).item()) / n
+        print(f"[large16384 {sch}] |dD|_F/N={fro:.3e} max={float(err.abs().max()):.3e} "
+              f"TrD={float(tr):.4f} (target {0.4 * n}) TrD64={float(tr64):.4f}", flush=True)
+        assert fro <= 1e-5
+        assert 0.0 <= float(tr2) <= float(tr) + 1e-6 * n
+        assert abs(float(tr) - 0.4 * n) < 0.01 * n
+        del D, err
+    monkeypatch.delenv("FE_SCHEDULE")
+    del D64
     torch.cuda.synchronize()
     ws.close()
