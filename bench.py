@@ -511,6 +511,23 @@ def bench_filling(args, torch, api, models, workloads, dev):
                       "N": n, "n_occ": n_occ, "layers": m.L,
                       "coefficients": "mlsp2_L26_b1500_mu1third", "precision": args.prec},
            "newton_iterations": iters, "mu": mu, "abs_trD_minus_n_occ": abs(float(tr) - n_occ)}
+    # the same solve with the bank model selected at the Newton start (the Gershgorin midpoint)
+    _, rinfo = api.rescale(Hd, 0.0, c["kT"], mref, want_X0=False, ws=ws)
+    mu_start = 0.5 * (rinfo["emin"] + rinfo["emax"])
+    bank = [models.load(x) for x in BANK]
+    bank_refs = [api.make_model(x.theta, x.beta0, x.mu0) for x in bank]
+    Db = torch.empty_like(D)
+
+    def solve_bank():
+        k = api.select_model(Hd, mu_start, c["kT"], bank_refs, ws=ws)
+        res["b"] = (k, api.expand_density_filling(Hd, n_occ, c["kT"], bank_refs[k], prec=args.prec,
+                                                  out=Db, ws=ws))
+    ms_b = timed(solve_bank, max(1, min(args.steps, 10)), 1, torch)
+    kb, (_, mu_b, iters_b, tr_b, _, _) = res["b"]
+    out["model_bank"] = {"model": BANK[kb], "layers": bank[kb].L, "ms_per_step": ms_b,
+                         "value": 1000.0 / ms_b, "newton_iterations": iters_b, "mu": mu_b,
+                         "abs_trD_minus_n_occ": abs(float(tr_b) - n_occ),
+                         "what": "model selection at the Newton start + Newton solve"}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         t0 = time.perf_counter()
@@ -521,6 +538,9 @@ def bench_filling(args, torch, api, models, workloads, dev):
         err = D.double().cpu().numpy() - ref["D"]
         out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
                                   "abs_dmu": abs(mu - mu_ref)}
+        err_b = Db.double().cpu().numpy() - ref["D"]
+        out["model_bank"]["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err_b) / n),
+                                                "abs_dmu": abs(mu_b - mu_ref)}
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "kind": "oracle",
                                "sample": "the full matrix: eigenvalues, bisection for mu, then "
                                          "eigendecomposition + assembly at that mu (FP64)"}
@@ -529,8 +549,8 @@ def bench_filling(args, torch, api, models, workloads, dev):
 
 def bench_variants(args, torch, api, models, workloads, dev):
     """Skip-SP2 (k = K = 1) and Max-SP2 on the N = 4096 Anderson workload (Sec. III.A), each the
-    App. C embedding of the 22-layer model the bank selects for this lattice (the same function
-    as the MLSP2 path): per layer one square-only split MFMA pass and one HBM-bound combine pass.
+    App. C embedding of the 22-layer beta0 = 600, mu0 = 1/3 model (the same function as that MLSP2
+    model): per layer one square-only split MFMA pass and one HBM-bound combine pass.
     Timed beside the fused MLSP2 path on the same matrix; errors against the oracle's exact D."""
     import numpy as np
 
