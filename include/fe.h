@@ -212,14 +212,15 @@ int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
 
 /* Rebuilds the plan (layout, tables, captured graph) with layer tiles of `tile` x `tile`, tile
  * 128 (the default: the single-matrix kernel's tiles) or 64 (32 x 32 per wave: less padding for
- * small matrices, more LDS traffic per flop). Results differ from the other tile size only by the
- * order of FP32 sums. */
+ * small matrices, more LDS traffic per flop). Results differ from the other tile size at most by
+ * the order of FP32 sums. Waits for the device first (a launch of the plan may be in flight), then
+ * replaces the captured graph; on failure the plan is left empty and its launches fail. */
 int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
 
 /* Autotunes the plan's tile size: builds it with each tile size, times three replays of each on
  * `stream` (after a warm-up), keeps the faster. tile (host, may be NULL) receives the choice, ms
  * (host, 2 entries, may be NULL) the ms per replay for tiles 128 and 64. Runs the batch 8 times;
- * synchronizes. */
+ * waits for the device first and synchronizes. */
 int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms);
 int fe_batch_plan_destroy(fe_batch_plan* plan);
 

@@ -425,12 +425,14 @@ int fe_batch_plan_destroy(fe_batch_plan* plan) {
 int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile) {
     if (!plan) return fail(FE_ERR_ARG, "invalid plan");
     if (tile != 64 && tile != 128) return fail(FE_ERR_ARG, "tile must be 64 or 128");
+    FE_HIP(hipDeviceSynchronize());   // a launch of the old graph may still be reading its tables
     return build_plan(plan, tile);
 }
 
 int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms) {
     if (!plan) return fail(FE_ERR_ARG, "invalid plan");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    FE_HIP(hipDeviceSynchronize());   // as in fe_batch_plan_retile
     const int cand[2] = {128, 64};
     double t_ms[2] = {0.0, 0.0};
     hipEvent_t e0 = nullptr, e1 = nullptr;
