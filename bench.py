@@ -29,12 +29,15 @@ METRIC = ("density matrices/s and TFLOP/s vs FP64 recursion & eigensolver at "
           "‖ΔD‖_F/N≤1e-5")
 PEAK_TFLOPS = {"fp16x2": 2500.0, "bf16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}
 HBM_GBS = 8000.0
-# The model bank: two trained families, mu0 = 1/3 and mu0 = 1/2 (each matrix runs the fewest
-# layers whose region of validity holds its (beta', mu'))
+# The model bank: trained families at mu0 = 1/3, 0.4 and 1/2, each fitted to <= 1e-7 max error
+# (each matrix runs the fewest layers whose region of validity holds its (beta', mu'))
 BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
-        "mlsp2_L40_b1e4_mu1third", "mlsp2_L18_b150_mu0p5", "mlsp2_L19_b200_mu0p5",
-        "mlsp2_L20_b300_mu0p5", "mlsp2_L22_b600_mu0p5", "mlsp2_L24_b1500_mu0p5",
-        "mlsp2_L36_b1e4_mu0p5"]
+        "mlsp2_L40_b1e4_mu1third",
+        "mlsp2_L18_b150_mu0p4", "mlsp2_L19_b200_mu0p4", "mlsp2_L20_b300_mu0p4",
+        "mlsp2_L22_b600_mu0p4", "mlsp2_L26_b1500_mu0p4",
+        "mlsp2_L18_b150_mu0p5", "mlsp2_L19_b200_mu0p5", "mlsp2_L20_b300_mu0p5",
+        "mlsp2_L22_b600_mu0p5", "mlsp2_L24_b1500_mu0p5", "mlsp2_L27_b3000_mu0p5",
+        "mlsp2_L29_b4000_mu0p5", "mlsp2_L36_b1e4_mu0p5"]
 
 
 def parse():
