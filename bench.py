@@ -66,6 +66,13 @@ def parse():
     return p.parse_args()
 
 
+def norm2_sym(E, torch, dev):
+    """Spectral norm of a symmetric error matrix (the paper's norm): max |eigenvalue|, FP64 on the
+    GPU (E: numpy array or tensor)."""
+    T = E if isinstance(E, torch.Tensor) else torch.from_numpy(E)
+    return float(torch.linalg.eigvalsh(T.to(device=dev, dtype=torch.float64)).abs().max().item())
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -333,10 +340,13 @@ def main():
                                "sample": "one full N=4096 matrix of the workload: LAPACK dsyevd "
                                          "eigendecomposition + V f V^T assembly in FP64 (numpy)"}
         err = Dg - ref["D"]
+        S_gpu = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
         out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
                                   "max_abs": float(np.max(np.abs(err))),
+                                  "norm2": norm2_sym(err, torch, dev),
                                   "abs_dTrD": abs(float(trD) - ref["trD"]),
-                                  "abs_dTrD2": abs(float(trD2) - ref["trD2"])}
+                                  "abs_dTrD2": abs(float(trD2) - ref["trD2"]),
+                                  "abs_dS": abs(S_gpu - ref["S"]), "S": ref["S"]}
         if Daff is not None:
             out["affine_form"]["fro_over_N_vs_oracle"] = float(np.linalg.norm(Daff - ref["D"]) / n)
     print(json.dumps(out), flush=True)
@@ -399,6 +409,7 @@ def bench_batch(args, torch, api, models, workloads, dev):
             Db = bplan.D[b].double().cpu().numpy()
             errs.append({"item": b, "N": it["n"],
                          "fro_over_N": float(np.linalg.norm(Dg - ref["D"]) / it["n"]),
+                         "norm2": float(np.max(np.abs(np.linalg.eigvalsh(Dg - ref["D"])))),
                          "abs_dTrD": abs(float(plan.tr[b, 0]) - ref["trD"]),
                          "bank_model": bank_names[int(bplan.chosen[b])],
                          "bank_fro_over_N": float(np.linalg.norm(Db - ref["D"]) / it["n"])})
@@ -474,6 +485,7 @@ def bench_large(args, torch, api, models, workloads, dev):
            "trD": float(trD), "trD_target": 0.4 * n,
            "vs_fp64_expansion": {"fro_over_N": float(torch.linalg.norm(err).item() / n),
                                  "max_abs": float(err.abs().max().item()),
+                                 "norm2": norm2_sym(err, torch, dev),
                                  "abs_dTrD": abs(float(trD) - float(trD64)),
                                  "abs_dS": abs(S - S64), "S": S},
            "model_bank": {"model": BANK[kb], "layers": bank[kb].L, "ms_per_step": ms_b,
@@ -540,6 +552,7 @@ def bench_filling(args, torch, api, models, workloads, dev):
         dt = time.perf_counter() - t0
         err = D.double().cpu().numpy() - ref["D"]
         out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
+                                  "norm2": norm2_sym(err, torch, dev),
                                   "abs_dmu": abs(mu - mu_ref)}
         err_b = Db.double().cpu().numpy() - ref["D"]
         out["model_bank"]["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err_b) / n),
