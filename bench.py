@@ -205,6 +205,17 @@ def main():
         return
 
     ms = timed(step, args.steps, args.warmup, torch)
+    # per-step distribution: events around each step of a second pass
+    per = []
+    for _ in range(max(20, args.steps)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        per.append((e0, e1))
+    torch.cuda.synchronize()
+    per_ms = sorted(a.elapsed_time(b) for a, b in per)
     ms_expand = timed(expand, args.steps, args.warmup, torch) if bank is not None else ms
     ms1 = timed(step1, args.steps, args.warmup, torch)
     L = m.L
@@ -254,6 +265,8 @@ def main():
         },
         "prologue_plus_one_layer_ms": ms1,
         "autotune": tuned,
+        "ms_per_step_median": per_ms[len(per_ms) // 2],
+        "ms_per_step_p90": per_ms[int(0.9 * (len(per_ms) - 1))],
     }
     # the whole single-matrix path of Alg. 2: density and entropy (theta_fermi reused for S,
     # alpha = 0.842704, as in the paper's Table I rows with theta_fermi)
@@ -332,13 +345,22 @@ def main():
                           if i.get("user_api") == "blas")
         except Exception:
             threads = os.cpu_count()
-        t0 = time.perf_counter()
-        ref = F.density(H, mu, kT)
-        dt = time.perf_counter() - t0
+        try:
+            blas = sorted({i.get("internal_api", "?") for i in threadpool_info()
+                           if i.get("user_api") == "blas"})
+        except Exception:
+            blas = []
+        dts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ref = F.density(H, mu, kT)
+            dts.append(time.perf_counter() - t0)
+        dt = sorted(dts)[1]
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "cores": threads,
-                               "kind": "oracle",
+                               "nproc": os.cpu_count(), "blas": blas, "kind": "oracle",
                                "sample": "one full N=4096 matrix of the workload: LAPACK dsyevd "
-                                         "eigendecomposition + V f V^T assembly in FP64 (numpy)"}
+                                         "eigendecomposition + V f V^T assembly in FP64 (numpy); "
+                                         "median of 3 runs"}
         err = Dg - ref["D"]
         S_gpu = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
         out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
