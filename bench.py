@@ -51,10 +51,12 @@ def parse():
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
     p.add_argument("--workload", default="anderson4096",
                    choices=["anderson4096", "batch1024", "large16384", "filling4096",
-                            "variants4096", "sweep"],
+                            "variants4096", "sweep", "train"],
                    help="anderson4096: the headline line (default); batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
-                        "density and entropy")
+                        "density and entropy; filling4096: Newton mu at half filling; "
+                        "variants4096: Skip-SP2 / Max-SP2; sweep: ms per D vs N; train: the "
+                        "coefficient fit and the matrix forward/backward")
     p.add_argument("--model", default="bank",
                    help="anderson4096: 'bank' (select per matrix, default) or one model name")
     p.add_argument("--vendor-gemm", action="store_true",
@@ -162,6 +164,8 @@ def main():
         return bench_variants(args, torch, api, models, workloads, dev)
     if args.workload == "sweep":
         return bench_sweep(args, torch, api, models, workloads, dev)
+    if args.workload == "train":
+        return bench_train(args, torch, api, models, workloads, dev)
     c = workloads.config_anderson_4096()
     H = c["H"]
     n = H.shape[0]
@@ -582,6 +586,61 @@ def bench_filling(args, torch, api, models, workloads, dev):
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "kind": "oracle",
                                "sample": "the full matrix: eigenvalues, bisection for mu, then "
                                          "eigendecomposition + assembly at that mu (FP64)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_train(args, torch, api, models, workloads, dev):
+    """Coefficient training at the 40-layer, beta0 = 1e4, mu0 = 1/3 setting (Sec. III.C): the
+    scalar Levenberg-Marquardt fit to the Fermi target on 8192 points (FP64 Jacobian kernel) from
+    the SP2 start, timed to its stop; then forward + backward passes of the FP32 matrix recursion
+    (torch.autograd.Function over fe_matrix_forward / fe_matrix_backward) over 64 matrices of the
+    random dense family at N = 256 (seeds 3000 + m, kT = 0.1, half filling), loss = sum of squared
+    errors against GPU FP64 eigendecomposition densities."""
+    import numpy as np
+
+    from paper_2605_08523_amd import training
+    L, beta0, mu0 = 40, 1e4, 1.0 / 3.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, rep, ok = training.train_coeffs(L, beta0, mu0, n_points=8192, max_iter=10000, tol=1e-10)
+    dt = time.perf_counter() - t0
+    out = {"metric": "LM iterations/s of the 40-layer coefficient fit (8192 points)",
+           "value": rep["iters"] / dt, "unit": "LM iterations/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "train_L40_b1e4_mu1third_8192pts", "layers": L, "beta0": beta0,
+                      "mu0": mu0, "points": 8192},
+           "iterations": rep["iters"], "seconds_to_stop": dt,
+           "ms_per_iteration": 1e3 * dt / max(1, rep["iters"]), "converged": bool(ok),
+           "max_error_grid": rep["max_err_grid"]}
+    # matrix-level passes
+    n, nm, kT = 256, 64, 0.1
+    model = api.make_model(th, beta0, mu0)
+    X0s, refs = [], []
+    for k in range(nm):
+        H = torch.from_numpy(workloads.random_dense(n, 3000 + k)).to(dev)
+        lam, V = torch.linalg.eigh(H)
+        mu = float(0.5 * (lam[n // 2 - 1] + lam[n // 2]))
+        X0, info = api.rescale(H, mu, kT, model, want_X0=True)
+        D = (V * torch.sigmoid(-(lam - mu) / kT)) @ V.T
+        refs.append(torch.eye(n, device=dev, dtype=torch.float64) - D if info["flipped"] else D)
+        X0s.append(X0.contiguous())
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+
+    def fwd_bwd():
+        theta.grad = None
+        loss = 0.0
+        for X0, Dr in zip(X0s, refs):
+            P = training.matrix_recursion(theta, X0)
+            loss = loss + ((P.double() - Dr) ** 2).sum()
+        loss.backward()
+        return float(loss.detach())
+    loss0 = fwd_bwd()
+    steps = max(2, min(args.steps, 10))
+    ms_mb = timed(fwd_bwd, steps, 1, torch)
+    out["matrix_fwd_bwd"] = {"matrices": nm, "N": n, "layers": L, "ms_per_pass": ms_mb,
+                             "ms_per_matrix": ms_mb / nm, "loss": loss0,
+                             "rms_error": float(np.sqrt(loss0 / (nm * n * n))),
+                             "grad_norm": float(theta.grad.norm())}
     print(json.dumps(out), flush=True)
 
 
