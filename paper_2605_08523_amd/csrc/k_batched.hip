@@ -27,9 +27,11 @@ __device__ inline double wmax(double v) {
     return v;
 }
 
-// One workgroup per matrix: Gershgorin bounds (one wave per row) and the rescale parameters of
-// Sec. IV.1, as in the single-matrix prologue.
-__global__ void __launch_bounds__(256)
+// One workgroup of 16 waves per matrix: Gershgorin bounds (one wave per row, each row summed in
+// the same order as the single-matrix prologue, so both give the same bounds) and the rescale
+// parameters of Sec. IV.1.
+constexpr int kBoundsWaves = 16;
+__global__ void __launch_bounds__(kBoundsWaves * 64)
 k_batch_bounds(const BatchMat* mats, int count, Params* P) {
     const int b = blockIdx.x;
     if (b >= count) return;
@@ -38,18 +40,26 @@ k_batch_bounds(const BatchMat* mats, int count, Params* P) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double lo = INFINITY, hi = -INFINITY;
     int bad = 0;
-    for (int64_t i = wave; i < m.n; i += 4) {
+    for (int64_t i = wave; i < m.n; i += kBoundsWaves) {
         const double* row = m.H + i * m.ldh;
-        double s = 0.0;
-        for (int64_t j = lane; j < m.n; j += 64) s += fabs(row[j]);
-        s = wsum(s);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int64_t j = lane;
+        for (; j + 192 < m.n; j += 256) {
+            s0 += fabs(row[j]);
+            s1 += fabs(row[j + 64]);
+            s2 += fabs(row[j + 128]);
+            s3 += fabs(row[j + 192]);
+        }
+        for (; j < m.n; j += 64) s0 += fabs(row[j]);
+        const double s = wsum((s0 + s1) + (s2 + s3));
         const double d = row[i];
+        const double r = s - fabs(d);
         if (!isfinite(s)) bad = 1;
-        lo = fmin(lo, d - (s - fabs(d)));
-        hi = fmax(hi, d + (s - fabs(d)));
+        lo = fmin(lo, d - r);
+        hi = fmax(hi, d + r);
     }
-    __shared__ double slo[4], shi[4];
-    __shared__ int sbad[4];
+    __shared__ double slo[kBoundsWaves], shi[kBoundsWaves];
+    __shared__ int sbad[kBoundsWaves];
     if (lane == 0) {
         slo[wave] = lo;
         shi[wave] = hi;
@@ -57,7 +67,7 @@ k_batch_bounds(const BatchMat* mats, int count, Params* P) {
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int w = 1; w < 4; ++w) {
+    for (int w = 1; w < kBoundsWaves; ++w) {
         lo = fmin(lo, slo[w]);
         hi = fmax(hi, shi[w]);
         bad |= sbad[w];
@@ -230,7 +240,7 @@ k_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials, co
 }  // namespace
 
 hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_bounds, dim3(count), dim3(256), 0, s, mats, count, P);
+    hipLaunchKernelGGL(k_batch_bounds, dim3(count), dim3(kBoundsWaves * 64), 0, s, mats, count, P);
     return hipGetLastError();
 }
 
