@@ -22,8 +22,8 @@
 //        registers);
 //      stream-K over 256 x 256 tiles (eight 128 x 64 wave tiles, two LDS stages filled by
 //        direct global-to-LDS loads, fragment reads interleaved with the MFMAs), one
-//        workgroup per CU: the same, with every segment's accumulators staged through memory
-//        right after its K loop (128 per lane would not survive the epilogue in registers).
+//        workgroup per CU: the same; its K loop holds no prefetch registers, so the 128
+//        accumulators per lane also stay in registers through the wait and the epilogue.
 //    A workgroup only ever waits for workgroups with smaller ids, which were dispatched earlier,
 //    and every wait is bounded.
 #include "split_common.h"
@@ -93,9 +93,10 @@ template <bool BF, class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_layer_sk(LayerArgs p, SplitPlan sk) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    // Small tiles keep their accumulators in registers through the wait; large ones (128
-    // accumulator registers per lane) stage them to memory right after the K loop.
-    constexpr bool kRegEpi = C::MB * C::NB <= 4;
+    // Accumulators stay in registers through the wait when the K loop leaves room for them
+    // (small tiles, or the direct-to-LDS loop, which holds no prefetch registers); otherwise
+    // (128 per lane next to a register-prefetch loop) they are staged to memory after the K loop.
+    constexpr bool kRegEpi = C::MB * C::NB <= 4 || C::DMA;
     const int tid = threadIdx.x;
     const int w = blockIdx.x;
     const int T = (int)(p.np / C::BM);
