@@ -62,3 +62,26 @@ def test_argument_errors_without_device(lib):
     rc = lib.fe_expand_density(None, 4, 4, 0.0, 0.1, None, 2, None, 0, 4, None, None, None, None, None)
     assert rc == api.FE_ERR_ARG
     assert lib.fe_version().startswith(b"fe-mi355x")
+
+
+def test_tuner_and_plan_argument_errors_without_device(lib):
+    """The tuners and batch-plan calls reject bad arguments before any device work."""
+    from paper_2605_08523_amd import api
+    i32 = ctypes.c_int32()
+    ms = (ctypes.c_double * 3)()
+    # fe_autotune_input: precision first, then the arguments of fe_expand_density
+    rc = lib.fe_autotune_input(None, 4, 4, 0.0, 0.1, None, api.PREC["fp32"], ctypes.byref(i32), ms,
+                               None, None)
+    assert rc == api.FE_ERR_ARG and b"16-bit" in lib.fe_last_error()
+    rc = lib.fe_autotune_input(None, 4, 4, 0.0, 0.1, None, api.PREC["fp16x2"], ctypes.byref(i32), ms,
+                               None, None)
+    assert rc == api.FE_ERR_ARG and b"workspace" in lib.fe_last_error()
+    # fe_autotune: no sizes; fe_autotune_lookup: no workspace
+    assert lib.fe_autotune(None, 0, api.PREC["fp16x2"], None, None, None, None) == api.FE_ERR_ARG
+    assert lib.fe_autotune_lookup(128, api.PREC["fp16x2"], None, ctypes.byref(i32)) == api.FE_ERR_ARG
+    assert lib.fe_autotune_clear() == api.FE_OK
+    # batch plans: NULL plan, bad tile size
+    assert lib.fe_batch_plan_retile(None, 64) == api.FE_ERR_ARG
+    assert lib.fe_batch_plan_autotune(None, None, ctypes.byref(i32), ms) == api.FE_ERR_ARG
+    assert lib.fe_batch_plan_launch(None, None) == api.FE_ERR_ARG
+    assert lib.fe_batch_plan_destroy(None) == api.FE_OK
