@@ -96,7 +96,8 @@ def test_split_modes_against_oracle(api, paper_model, prec, name, make):
 
 
 def test_anderson_4096_fp16x2(api, paper_model):
-    """The benchmark workload at full size, in the launch configuration the benchmark times."""
+    """The benchmark workload at full size, in the launch configuration the benchmark times: the
+    paper's 26-layer model, then the model the benchmark's bank selects (FP16x2 and BF16x2)."""
     m = paper_model
     c = W.config_anderson_4096()
     print("case anderson4096 fp16x2", flush=True)
@@ -106,6 +107,20 @@ def test_anderson_4096_fp16x2(api, paper_model):
     fro, _ = report("anderson4096 fp16x2 vs exact", D, exact["D"], tr, exact["trD"])
     assert fro <= 1e-5
     assert torch.equal(Dt, Dt.T)
+    # the benchmark's step: the model the bank selects for this lattice, both 16-bit splits
+    import bench
+    from paper_2605_08523_amd import models
+    bank = [models.load(x) for x in bench.BANK]
+    Hd = torch.from_numpy(c["H"]).cuda()
+    k = api.select_model(Hd, c["mu"], c["kT"], bank)
+    assert bench.BANK[k] == "mlsp2_L20_b300_mu0p5"
+    for prec in ("fp16x2", "bf16x2"):
+        print(f"case anderson4096 {prec} bank model {bench.BANK[k]}", flush=True)
+        D, tr, tr2, info, Dt = run(api, c["H"], c["mu"], c["kT"], bank[k], prec)
+        assert info["rc"] == 0
+        fro, _ = report(f"anderson4096 {prec} bank vs exact", D, exact["D"], tr, exact["trD"])
+        assert fro <= 1e-5
+        assert torch.equal(Dt, Dt.T)
 
 
 def test_strided_inputs_and_fp64_output(api, paper_model):
