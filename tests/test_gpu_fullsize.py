@@ -1,8 +1,8 @@
 """Full-size configurations, in the launch configuration bench.py times.
 
-* The batch of 1024 uneven matrices (N_b ~ U{64..768}, 40-layer model at beta0 = 1e4): every
-  item's status, and sampled items (the smallest, the largest and three seeded picks) against the
-  oracle's eigendecomposition, element by element.
+* The batch of 1024 uneven matrices (N_b ~ U{64..768}), with the 40-layer model at beta0 = 1e4
+  and over the benchmark's model bank: every item's status, and sampled items (the smallest, the
+  largest and three seeded picks) against the oracle's eigendecomposition, element by element.
 * One N = 16384 solve: the oracle's eigendecomposition would take tens of minutes, so the FP16x2
   result is checked against the FP64 expansion on the GPU (itself pinned to the oracle at smaller
   sizes) and against properties that hold at any size (exact symmetry, 0 <= sum D_ij^2 <= Tr D,
@@ -50,6 +50,26 @@ def test_batch1024_sampled_against_oracle(api):
               f"|dTrD|={abs(float(plan.tr[b, 0]) - ref['trD']):.3e}", flush=True)
         assert fro <= 1e-5
         assert np.array_equal(Dg, Dg.T)
+    # the same batch over the benchmark's model bank (each matrix runs its selected model)
+    import bench
+    bank = [models.load(x) for x in bench.BANK]
+    plan.close()
+    print("case batch1024 fp16x2 bank", flush=True)
+    bplan = api.BatchPlan(mats, bank, prec="fp16x2", ws=plan.ws)
+    bplan.launch()
+    torch.cuda.synchronize()
+    assert int(np.count_nonzero(bplan.status.cpu().numpy())) == 0
+    assert len(set(bplan.chosen.tolist())) >= 5
+    for b in sample:
+        it = items[b]
+        ref = F.density(it["H"], it["mu"], it["kT"])
+        Dg = bplan.D[b].double().cpu().numpy()
+        fro = np.linalg.norm(Dg - ref["D"]) / it["n"]
+        print(f"[batch1024 bank item {b}] N={it['n']} model {bench.BANK[int(bplan.chosen[b])]} "
+              f"|dD|_F/N={fro:.3e}", flush=True)
+        assert fro <= 1e-5
+        assert np.array_equal(Dg, Dg.T)
+    bplan.close()
 
 
 def test_large16384_against_fp64_expansion(api, monkeypatch):
