@@ -105,5 +105,22 @@ def test_large16384_against_fp64_expansion(api, monkeypatch):
         del D, err
     monkeypatch.delenv("FE_SCHEDULE")
     del D64
+    # the model the benchmark's bank selects for this matrix, against its own FP64 expansion
+    import bench
+    bank = [models.load(x) for x in bench.BANK]
+    k = api.select_model(Hd, mu, kT, bank, ws=ws)
+    mb = bank[k]
+    print(f"case large16384 bank model {bench.BANK[k]}", flush=True)
+    assert mb.L < m.L
+    D, tr, _, info = api.expand_density(Hd, mu, kT, mb, prec="fp16x2", ws=ws, want_info=True)
+    D64, _, _, _ = api.expand_density(Hd, mu, kT, mb, prec="fp64", ws=ws, out_dtype=torch.float64,
+                                      want_info=True)
+    torch.cuda.synchronize()
+    assert info["clamped"] == 0
+    fro = float(torch.linalg.norm(D.double() - D64).item()) / n
+    print(f"[large16384 bank {bench.BANK[k]}] |dD|_F/N={fro:.3e} TrD={float(tr):.4f}", flush=True)
+    assert fro <= 1e-5
+    assert abs(float(tr) - 0.4 * n) < 0.01 * n
+    del D, D64
     torch.cuda.synchronize()
     ws.close()
