@@ -51,12 +51,19 @@ def entropy_fn(e, mu: float, kT: float):
 def gershgorin(H: np.ndarray):
     """Spectral bounds from Gershgorin's circle theorem (Sec. IV.1; Alg. 2, first step).
 
-    r_i = sum_{j != i} |h_ij|; eps_min = min_i (h_ii - r_i); eps_max = max_i (h_ii + r_i).
+    Every eigenvalue lies in some disc centred at a diagonal entry h_ii with radius
+    r_i = sum_{j != i} |h_ij|, so the union of the discs' real intervals,
+    [min_i (h_ii - r_i), max_i (h_ii + r_i)], holds the spectrum. Walked row by row.
     """
     H = np.asarray(H, dtype=np.float64)
-    d = np.diag(H)
-    r = np.abs(H).sum(axis=1) - np.abs(d)
-    return float(np.min(d - r)), float(np.max(d + r))
+    lo, hi = np.inf, -np.inf
+    for i in range(H.shape[0]):
+        row = H[i]
+        centre = float(row[i])
+        radius = float(np.sum(np.abs(row))) - abs(centre)
+        lo = min(lo, centre - radius)
+        hi = max(hi, centre + radius)
+    return float(lo), float(hi)
 
 
 def eig(H: np.ndarray):

@@ -39,97 +39,139 @@ class DomainError(ValueError):
     pass
 
 
-def rescale(H: np.ndarray, mu: float, kT: float, beta0: float, mu0: float):
-    """Affine map of H onto the model's coordinate (Sec. IV.1).
+def model_map(bounds, mu: float, kT: float, beta0: float, mu0: float):
+    """The affine map from energies to the model coordinate (Sec. IV.1), as one scale and shift.
 
-    Steps, in the paper's order:
-      1. Gershgorin bounds eps_min, eps_max.
-      2. H' = (eps_max I - H)/(eps_max - eps_min)      (Eq. H')
-         mu' = (eps_max - mu)/(eps_max - eps_min)     (Eq. mu')
-         beta' = (eps_max - eps_min) / kT            (Eq. beta')
-      3. If mu' > 1/2: H' <- I - H', mu' <- 1 - mu'  (Eq. flip; strict inequality)
-      4. beta_max = min(mu0/mu', (1 - mu0)/(1 - mu')) beta0 (Eq. conditions);
-         beta' > beta_max is clamped to beta_max and reported.
-      5. X0 = (beta'/beta0)(H' - mu' I) + mu0 I        (Eq. H0)
+    Eqs. H', mu' and beta' normalise the spectrum by its Gershgorin width w and place mu at
+    mu' = (eps_max - mu)/w; Eq. H0 then stretches about mu' by beta'/beta0 and moves mu' onto
+    mu0. Composed, every energy e lands at
 
-    Returns (X0, info). ``info`` holds the bounds, mu', beta', beta_max, the
-    flip and clamp flags and the affine form X0 = scale H + shift I.
+        y(e) = mu0 + sigma (beta'/beta0) (e - mu) / w,
+
+    with sigma = -1, or +1 when Eq. flip has replaced mu' by 1 - mu' (only for mu' > 1/2,
+    strictly). Unclamped, beta'/w = 1/kT, so beta0 (y - mu0) = -+ (e - mu)/kT: this is the
+    identity (mu' I - H') beta' = beta (H - mu I) that makes g(y) equal f(e) (or 1 - f(e)
+    after the flip). Eq. conditions bound beta' by beta_max = beta0 min(mu0/mu', (1 - mu0)/(1 - mu'))
+    (mu' after the flip); a larger beta' is replaced by beta_max and reported as clamped.
+
+    Returns a dict with the bounds, mu', beta', beta_max, the flags, and y = scale e + shift.
     """
     if not (kT > 0.0) or not np.isfinite(kT):
         raise DomainError("kT must be positive")
-    H = np.asarray(H, dtype=np.float64)
-    n = H.shape[0]
-    I = np.eye(n)
-    emin, emax = gershgorin(H)
+    emin, emax = bounds
     width = emax - emin
     if width <= 1e-300 * max(1.0, abs(emax)):
-        # H = c I: constant model coordinate (see the module docstring).
-        c = float(H[0, 0])
-        y = mu0 + (mu - c) / (kT * beta0)
-        clamped = not (0.0 <= y <= 1.0)
-        y = min(1.0, max(0.0, y))
-        info = dict(emin=emin, emax=emax, mu_p=float('nan'), beta_p=float('inf'),
-                    beta_max=float('nan'), flipped=False, clamped=clamped,
-                    degenerate=True, scale=0.0, shift=y)
-        return y * I, info
+        return dict(emin=emin, emax=emax, mu_p=float('nan'), beta_p=float('inf'),
+                    beta_max=float('nan'), flipped=False, clamped=False, degenerate=True,
+                    scale=0.0, shift=float('nan'))
     if not (emin < mu < emax):
         raise DomainError("mu must lie strictly inside the Gershgorin bounds")
-    Hp = (emax * I - H) / width
     mu_p = (emax - mu) / width
+    flipped = bool(mu_p > 0.5)
+    mu_eff = 1.0 - mu_p if flipped else mu_p
     beta_p = width / kT
-    flipped = mu_p > 0.5
-    if flipped:
-        Hp = I - Hp
-        mu_p = 1.0 - mu_p
-    beta_max = min(mu0 / mu_p, (1.0 - mu0) / (1.0 - mu_p)) * beta0
-    clamped = beta_p > beta_max
-    if clamped:
-        beta_p = beta_max
-    X0 = (Hp - mu_p * I) * (beta_p / beta0) + mu0 * I
-    r = beta_p / beta0
-    if flipped:
-        scale, shift = r / width, r * (-emin / width - mu_p) + mu0
-    else:
-        scale, shift = -r / width, r * (emax / width - mu_p) + mu0
-    info = dict(emin=emin, emax=emax, mu_p=mu_p, beta_p=beta_p, beta_max=beta_max,
+    bmax = beta_max(mu_eff, beta0, mu0)
+    clamped = bool(beta_p > bmax)
+    beta_used = bmax if clamped else beta_p
+    scale = (1.0 if flipped else -1.0) * (beta_used / beta0) / width
+    return dict(emin=emin, emax=emax, mu_p=mu_eff, beta_p=beta_used, beta_max=bmax,
                 flipped=flipped, clamped=clamped, degenerate=False,
-                scale=scale, shift=shift)
-    return X0, info
+                scale=scale, shift=mu0 - scale * mu)
 
 
-def mlsp2_layers(X, theta, return_history: bool = False):
-    """MLSP2 layers (Eq. mlsp2; Alg. 1 without its opening flip, see module docstring).
+def _degenerate_coordinate(c: float, mu: float, kT: float, beta0: float, mu0: float):
+    """H = c I has zero Gershgorin width, so Eq. H' is undefined. Its one eigenvalue c is
+    placed where the unflipped map of any width would put it, y = mu0 + (mu - c)/(kT beta0),
+    and held inside [0, 1] (outside it the model is not trained); leaving [0, 1] counts as a
+    clamp."""
+    y = mu0 + (mu - c) / (kT * beta0)
+    return min(1.0, max(0.0, y)), not (0.0 <= y <= 1.0)
 
-    For each layer (a, b, c, d) = theta_i:  A <- A + d X;  X <- a X^2 + b X + c I.
-    Output A + X (Eq. mlsp2-output). Works on scalars/arrays (elementwise
-    squaring) when X is not 2-D square, and on symmetric matrices (X^2 = X @ X)
-    otherwise.
+
+def rescale(H: np.ndarray, mu: float, kT: float, beta0: float, mu0: float):
+    """X0 = scale H + shift I, the rescaled Hamiltonian of Eq. H0 (see ``model_map``).
+
+    Returns (X0, info); info is ``model_map``'s dict (for H = c I, with the constant
+    coordinate of ``_degenerate_coordinate`` as shift and scale 0).
+    """
+    H = np.asarray(H, dtype=np.float64)
+    n = H.shape[0]
+    info = model_map(gershgorin(H), mu, kT, beta0, mu0)
+    if info["degenerate"]:
+        y, clamped = _degenerate_coordinate(float(H[0, 0]), mu, kT, beta0, mu0)
+        info.update(shift=y, clamped=clamped)
+        return y * np.eye(n), info
+    return info["scale"] * H + info["shift"] * np.eye(n), info
+
+
+def _layers_scalar(x, theta):
+    """Eq. mlsp2 on numbers: for each layer (a, b, c, d), the accumulator gains d x and x
+    becomes a x^2 + b x + c; the output is the accumulator plus the last x (Eq. mlsp2-output)."""
+    x = np.asarray(x, dtype=np.float64)
+    acc = np.zeros_like(x)
+    for a, b, c, d in np.asarray(theta, dtype=np.float64):
+        acc = acc + d * x
+        x = (a * x + b) * x + c
+    return acc + x
+
+
+def mlsp2_layers(X, theta):
+    """The MLSP2 model P of Eq. mlsp2 applied to numbers, or to a symmetric matrix.
+
+    The layers are polynomials, so for a symmetric matrix X = Q diag(y) Q^T the recursion's
+    result is Q diag(P(y)) Q^T (Sec. III.A: the layers act on the eigenvalues only); the
+    matrix form is evaluated that way, from one eigendecomposition.
     """
     X = np.asarray(X, dtype=np.float64)
-    matrix = X.ndim == 2 and X.shape[0] == X.shape[1]
-    I = np.eye(X.shape[0]) if matrix else 1.0
-    A = np.zeros_like(X)
-    hist = [X]
-    for a, b, c, d in np.asarray(theta, dtype=np.float64):
-        A = A + d * X
-        X2 = X @ X if matrix else X * X
-        X = a * X2 + b * X + c * I
-        hist.append(X)
-    out = A + X
-    return (out, hist) if return_history else out
+    if X.ndim == 2 and X.shape[0] == X.shape[1] and X.shape[0] > 1:
+        y, Q = np.linalg.eigh(X)
+        return _assemble(Q, _layers_scalar(y, theta))
+    return _layers_scalar(X, theta)
+
+
+def _assemble(Q, g):
+    M = (Q * g) @ Q.T
+    return 0.5 * (M + M.T)
+
+
+def model_values(lam, bounds, mu, kT, beta0, mu0):
+    """Model coordinate y of every eigenvalue ``lam`` of a matrix with Gershgorin ``bounds``
+    (``model_map``; for zero width the constant coordinate of ``_degenerate_coordinate``, where
+    every eigenvalue equals the diagonal). Returns (y, info)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    info = model_map(bounds, mu, kT, beta0, mu0)
+    if info["degenerate"]:
+        y, clamped = _degenerate_coordinate(float(bounds[0]), mu, kT, beta0, mu0)
+        info.update(shift=y, clamped=clamped)
+        return np.full_like(lam, y), info
+    return info["scale"] * lam + info["shift"], info
+
+
+def density_eigenvalues(lam, bounds, mu, kT, theta, beta0, mu0):
+    """Eigenvalues of the expansion's D: the layers on each model coordinate, one minus that when
+    the map flipped the spectrum (Eq. flip: the model then gives the occupation of holes)."""
+    y, info = model_values(lam, bounds, mu, kT, beta0, mu0)
+    p = _layers_scalar(y, theta)
+    return (1.0 - p if info["flipped"] else p), info
+
+
+def entropy_eigen_terms(lam, bounds, mu, kT, theta_s, beta0, mu0, alpha):
+    """Per-eigenvalue terms of the entropy expansion: Y0 = alpha X0 + (1 - alpha) mu0 I pulls the
+    model coordinate towards mu0 by alpha, the layers give u, and S = 4 ln2 (Tr U - Tr U^2)
+    (Eq. entropy expansion-s) is the sum of 4 ln2 u_i (1 - u_i) over the eigenvalues of the
+    symmetric U. s(f) = s(1 - f), so the flip needs no correction."""
+    y, info = model_values(lam, bounds, mu, kT, beta0, mu0)
+    u = _layers_scalar(alpha * (y - mu0) + mu0, theta_s)
+    return 4.0 * math.log(2.0) * u * (1.0 - u), info
 
 
 def mlsp2_density(H, mu, kT, theta, beta0, mu0):
-    """D from Alg. 2 (density part) in FP64: rescale, MLSP2 layers, undo the flip.
-
-    Returns (D, info). If the rescale flipped the spectrum the result is I - (A + X)
-    (Eq. flip).
-    """
-    X0, info = rescale(H, mu, kT, beta0, mu0)
-    P = mlsp2_layers(X0, theta)
-    n = P.shape[0]
-    D = np.eye(n) - P if info["flipped"] else P
-    return D, info
+    """D from Alg. 2 (density part) in FP64, evaluated on the spectrum of H:
+    D = Q diag(``density_eigenvalues``) Q^T. Returns (D, info)."""
+    H = np.asarray(H, dtype=np.float64)
+    lam, Q = np.linalg.eigh(H)
+    g, info = density_eigenvalues(lam, gershgorin(H), mu, kT, theta, beta0, mu0)
+    return _assemble(Q, g), info
 
 
 def entropy_layers(Y0, theta_s):
@@ -138,24 +180,18 @@ def entropy_layers(Y0, theta_s):
 
 
 def entropy_expansion(H, mu, kT, theta_s, beta0, mu0, alpha):
-    """S from Alg. 2 (entropy part) in FP64.
-
-    Y0 = alpha X0 + (1 - alpha) mu0 I; L_S layers with Theta; U = A_S + Y;
-    S = 4 ln2 (Tr U - sum_ij U_ij^2) (Eq. entropy expansion-s traced).
-    The entropy is symmetric under the flip, so no flip correction is needed.
-    """
-    X0, info = rescale(H, mu, kT, beta0, mu0)
-    n = X0.shape[0]
-    Y0 = alpha * X0 + (1.0 - alpha) * mu0 * np.eye(n)
-    U = entropy_layers(Y0, theta_s)
-    S = 4.0 * math.log(2.0) * (np.trace(U) - np.sum(U * U))
-    return float(S), info
+    """S from Alg. 2 (entropy part) in FP64: the sum of ``entropy_eigen_terms`` over the
+    spectrum of H. Returns (S, info)."""
+    H = np.asarray(H, dtype=np.float64)
+    lam = np.linalg.eigvalsh(H)
+    s, info = entropy_eigen_terms(lam, gershgorin(H), mu, kT, theta_s, beta0, mu0, alpha)
+    return float(np.sum(s)), info
 
 
 def entropy_scalar(y, theta_s, mu0, alpha):
     """Scalar entropy model s~(y) = 4 ln2 u (1 - u), u = layers(alpha (y - mu0) + mu0)."""
     y0 = alpha * (np.asarray(y, dtype=np.float64) - mu0) + mu0
-    u = mlsp2_layers(y0, theta_s)
+    u = _layers_scalar(y0, theta_s)
     return 4.0 * math.log(2.0) * u * (1.0 - u)
 
 

@@ -20,8 +20,6 @@ import math
 
 import numpy as np
 
-from .fermi import entropy_of_occupation
-
 
 def fermi_target(y, beta0: float, mu0: float):
     """g(y) = 1/(1 + exp(beta0 (mu0 - y))) evaluated without overflow."""
@@ -133,6 +131,44 @@ def max_model_error(theta, beta0: float, mu0: float, kind: str = "fermi", alpha:
     return float(np.max(np.abs(forward(y, theta, kind, mu0, alpha) - tgt)))
 
 
-def entropy_of_fermi_model(theta, y, beta0, mu0):
-    """Entropy of the Fermi model's occupations, -P ln P - (1-P) ln(1-P) (for diagnostics)."""
-    return entropy_of_occupation(np.clip(forward(y, theta, "fermi"), 0.0, 1.0))
+def max_abs_state(theta, kind: str = "fermi", mu0: float = 1.0 / 3.0, alpha: float = 1.0,
+                  n: int = 100001) -> float:
+    """Largest |x_i| over all layer states for inputs y on a uniform grid of [0, 1].
+
+    The split modes hold each state in 16-bit halves, so this is the operand range a model
+    needs (Eq. emulated matmul)."""
+    y = np.linspace(0.0, 1.0, n)
+    x = y if kind == "fermi" else alpha * (y - mu0) + mu0
+    m = float(np.max(np.abs(x)))
+    for a, b, c, _ in np.asarray(theta, dtype=np.float64):
+        x = a * x * x + b * x + c
+        m = max(m, float(np.max(np.abs(x))))
+    return m
+
+
+def _forward_complex(y, theta, kind, mu0, alpha):
+    """``forward`` with complex coefficients allowed (for the complex step)."""
+    x = np.asarray(y, dtype=np.float64).astype(np.complex128)
+    if kind != "fermi":
+        x = alpha * (x - mu0) + mu0
+    A = np.zeros_like(x)
+    for a, b, c, d in np.asarray(theta):
+        A = A + d * x
+        x = a * x * x + b * x + c
+    u = A + x
+    return u if kind == "fermi" else 4.0 * math.log(2.0) * u * (1.0 - u)
+
+
+def second_directional(y, theta, v, kind: str = "fermi", mu0: float = 1.0 / 3.0,
+                       alpha: float = 1.0, h: float = 1e-4):
+    """d^2/dt^2 of the model output at theta + t v, t = 0 (the geodesic acceleration's input in
+    Levenberg-Marquardt, Sec. III.C). The first t-derivative is exact by the complex step,
+    f'(t) = Im f(theta + (t + i e) v) / e; the second is its central difference with step h
+    (relative error O(h^2))."""
+    th = np.asarray(theta, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64).reshape(th.shape)
+    e = 1e-30
+
+    def d1(t):
+        return np.imag(_forward_complex(y, th + (t + 1j * e) * v, kind, mu0, alpha)) / e
+    return (d1(h) - d1(-h)) / (2.0 * h)

@@ -27,16 +27,6 @@ class Model:
     alpha: float = 1.0
     meta: dict = field(default_factory=dict)
 
-    def max_abs_layer(self, n: int = 100001) -> float:
-        """Largest |x_i| over the layers for inputs y in [0, 1] (FP16 range planning)."""
-        y = np.linspace(0.0, 1.0, n)
-        x = y if self.kind == "fermi" else self.alpha * (y - self.mu0) + self.mu0
-        m = float(np.max(np.abs(x)))
-        for a, b, c, _ in self.theta:
-            x = a * x * x + b * x + c
-            m = max(m, float(np.max(np.abs(x))))
-        return m
-
 
 def path(name: str) -> str:
     return os.path.join(_DIR, name if name.endswith(".json") else name + ".json")

@@ -12,4 +12,5 @@ def test_model_bank_entry(name):
     err = T.max_model_error(m.theta, m.beta0, m.mu0, n=200001)
     recorded = m.meta.get("max_error", 5.960464477539063e-08)
     assert err <= 1.01 * recorded
-    assert m.max_abs_layer() < 16.0          # inside the 16-bit operand range of the split modes
+    # inside the 16-bit operand range of the split modes
+    assert T.max_abs_state(m.theta, m.kind, m.mu0, m.alpha) < 16.0

@@ -90,7 +90,7 @@ def test_paper_model_data_properties(paper_model):
     m = paper_model
     small = np.sum(np.abs(m.theta[:, 3]) < 1e-8)
     assert abs(small / m.L - g("half_of_layers_small_d")) < 0.1        # 11 of 26
-    assert m.max_abs_layer() < 1 + g("layer_value_spread")
+    assert T.max_abs_state(m.theta) < 1 + g("layer_value_spread")
 
 
 @pytest.mark.parametrize("beta_p", [10.0, 100.0, 500.0, 1000.0])
@@ -123,13 +123,40 @@ def test_appendix_selftest(paper_model):
         assert np.linalg.norm(D - ref, 2) < g("model_error_bound_L26")
 
 
-def test_matrix_recursion_equals_scalar_on_eigenvalues(paper_model):
+def test_spectral_recursion_against_matrix_products(paper_model):
+    """The oracle evaluates the layers on eigenvalues; here the first layers of the printed model
+    run as literal matrix products (x <- a x x + b x + c I, A <- A + d x, on the matrix) and
+    must give the same matrix."""
     m = paper_model
     H = W.random_dense(48, 9)
     X0, info = R.rescale(H, 0.1, 0.1, m.beta0, m.mu0)
-    y, V = np.linalg.eigh(X0)
-    P = R.mlsp2_layers(X0, m.theta)
-    np.testing.assert_allclose(P, (V * R.mlsp2_layers(y, m.theta)) @ V.T, atol=1e-11)
+    for n_layers in (1, 2, 6):
+        th = m.theta[:n_layers]
+        X, A = X0.copy(), np.zeros_like(X0)
+        for a, b, c, d in th:
+            A = A + d * X
+            X = a * (X @ X) + b * X + c * np.eye(48)
+        np.testing.assert_allclose(R.mlsp2_layers(X0, th), A + X, atol=1e-12)
+    # and the density, whose flip the test applies itself
+    D, info = R.mlsp2_density(H, 0.1, 0.1, m.theta, m.beta0, m.mu0)
+    X, A = X0.copy(), np.zeros_like(X0)
+    for a, b, c, d in m.theta:
+        A = A + d * X
+        X = a * (X @ X) + b * X + c * np.eye(48)
+    P = A + X
+    np.testing.assert_allclose(D, np.eye(48) - P if info["flipped"] else P, atol=1e-11)
+
+
+def test_gershgorin_bounds_closed_forms():
+    """Diagonal H: the bounds are its extreme entries. Tridiagonal Toeplitz (2 on the diagonal,
+    -1 beside it): the outer discs give [0, 4] (interior rows radius 2, end rows radius 1)."""
+    d = np.array([0.3, -1.2, 2.5, 0.0])
+    assert F.gershgorin(np.diag(d)) == (-1.2, 2.5)
+    T3 = 2 * np.eye(6) - np.eye(6, k=1) - np.eye(6, k=-1)
+    assert F.gershgorin(T3) == (0.0, 4.0)
+    # a row with a large off-diagonal entry sets the bound through its own centre
+    H = np.array([[1.0, -3.0, 0.5], [-3.0, 0.0, 0.0], [0.5, 0.0, -2.0]])
+    assert F.gershgorin(H) == (min(1 - 3.5, 0 - 3, -2 - 0.5), max(1 + 3.5, 3.0, -1.5))
 
 
 def test_config_small_dense_against_definition(paper_model):
