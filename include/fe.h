@@ -402,6 +402,29 @@ int fe_sp2_coeffs(double mu_p, int32_t L, double* theta_out);
  * (Sec. V.B, Eq. layer count). */
 double fe_layer_count(double beta_p);
 
+/* ---- diagnostics ------------------------------------------------------------------------ */
+
+/* The stream-K work split of the 16-bit layer kernel (the split of each layer's (tile, K-block)
+ * iterations over persistent workgroups that balances the last round of X^2 tiles, Sec. V.A's
+ * layer GEMM), evaluated on the host by the same code the kernel runs; no device work.
+ * np: padded size, a positive multiple of the schedule's tile (256 for schedule 1, 128 for 2).
+ * schedule: 1 (256 x 256 tiles) or 2 (128 x 128 tiles). grid: the workgroups offered (the
+ * library offers one per CU for schedule 1, two for schedule 2). geom: host int32[6], receives
+ * T (tiles per side), ntiles, nk (K-blocks per tile), dp_tiles (leading tiles computed whole
+ * before the stream-K launch), groups and the grid actually launched. w: a workgroup of that
+ * grid (outside it: *count = 0). segs: host int32[5 * cap] or NULL, receives w's segments in run
+ * order as (pass, tile, kb0, kb1, jlo): pass 0 publishes blocks [kb0, kb1) of the tile as a
+ * partial, passes 1 and 2 finish the tile after adding the partials of the group's workgroups
+ * jlo .. (w / groups) - 1 (ids w % groups + groups jj). count: host, the number of segments. */
+int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, int32_t* geom,
+                        int32_t* segs, int32_t cap, int32_t* count);
+
+/* Test hook for failure handling (process-wide): while enabled, every stream-K wait of the layer
+ * kernel waits for a flag value that no workgroup writes and gives up after a short bounded spin,
+ * as a wait that timed out would. Every kernel still exits normally; the tiles finished after a
+ * give-up are NaN, the traces NaN, and the rescale info status FE_ERR_HIP. */
+int fe_debug_streamk_giveup(int32_t enable);
+
 /* Message for the last error on the calling thread (static storage, never NULL). */
 const char* fe_last_error(void);
 

@@ -99,6 +99,9 @@ SIGNATURES = {
     "fe_embed_mlsp2": (_I32, [C.POINTER(fe_model), _I32, C.POINTER(_D)]),
     "fe_variant_eval": (_I32, [_P, _I32, C.POINTER(fe_qmodel), _P, _P, _P, _P, _P]),
     "fe_train_variant": (_I32, [_P, C.POINTER(fe_qmodel), C.POINTER(_D), _P, _P]),
+    "fe_streamk_segments": (_I32, [_I64, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _I32,
+                                   C.POINTER(_I32)]),
+    "fe_debug_streamk_giveup": (_I32, [_I32]),
     "fe_last_error": (C.c_char_p, []),
     "fe_version": (C.c_char_p, []),
 }
@@ -411,6 +414,26 @@ def layer_count(beta_p: float) -> float:
 
 def version() -> str:
     return lib().fe_version().decode()
+
+
+def streamk_segments(np_: int, schedule: int, grid: int, w: int):
+    """fe_streamk_segments: (geometry dict, int32 array of w's segments, one row (pass, tile,
+    kb0, kb1, jlo) each), computed on the host."""
+    geom = (C.c_int32 * 6)()
+    cnt = C.c_int32()
+    _check(lib().fe_streamk_segments(int(np_), int(schedule), int(grid), int(w), geom, None, 0,
+                                     C.byref(cnt)))
+    segs = np.zeros((max(cnt.value, 1), 5), dtype=np.int32)
+    _check(lib().fe_streamk_segments(int(np_), int(schedule), int(grid), int(w), geom,
+                                     segs.ctypes.data_as(C.POINTER(C.c_int32)), cnt.value,
+                                     C.byref(cnt)))
+    g = dict(zip(("T", "ntiles", "nk", "dp_tiles", "groups", "grid"), list(geom)))
+    return g, segs[:cnt.value]
+
+
+def debug_streamk_giveup(enable: bool) -> None:
+    """fe_debug_streamk_giveup: make every stream-K wait give up (failure-handling tests)."""
+    _check(lib().fe_debug_streamk_giveup(1 if enable else 0))
 
 
 # ---- batches -----------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -41,6 +42,9 @@ struct TunedEntry {
 };
 std::mutex g_tune_mu;
 std::vector<TunedEntry> g_tuned;
+// fe_debug_streamk_giveup: stream-K waits expect a flag value that is never written
+std::atomic<int> g_sk_giveup{0};
+constexpr uint32_t kNeverEpoch = 0xFFFFFFFFu;   // no launch publishes this value
 thread_local int t_forced_schedule = -1;   // set by the tuner around its timing runs
 
 int tuned_schedule(int device, int prec, int64_t n) {
@@ -199,8 +203,12 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             la.out_mode = out_mode; la.entropy = entropy; la.D = D; la.ldd = ldd;
             la.P = P; la.partials = tp;
             if (plan.streamk) {
-                if (++ws->epoch == 0) ++ws->epoch;   // flags start at 0: never reuse 0
+                // flags start at 0, and kNeverEpoch is reserved: neither is ever published
+                if (++ws->epoch == 0 || ws->epoch == kNeverEpoch) ws->epoch = 1;
                 plan.epoch = ws->epoch;
+                const bool giveup = g_sk_giveup.load() != 0;
+                plan.wait_epoch = giveup ? kNeverEpoch : plan.epoch;
+                plan.spin_limit = giveup ? 64 : (1 << 22);   // 1 << 22: ~0.2 s of sleeps
             }
             FE_HIP(fe::launch_layer_split(la, bf, plan, s));
         }
@@ -235,7 +243,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             FE_HIP(f64 ? fe::launch_layer_f64(wa, s) : fe::launch_layer_f32(wa, s));
         }
     }
-    FE_HIP(fe::launch_reduce_partials(tp, npart, trD, trD2, S, P, s));
+    FE_HIP(fe::launch_reduce_partials(tp, npart, trD, trD2, S, P, ws->sk_err, s));
     if (info) return read_info(ws, which, s, info);
     return FE_OK;
 }
@@ -446,7 +454,7 @@ int time_schedules(const double* H, int64_t n, int64_t ldh, double mu, double kT
     int rc = FE_OK;
     const int cands = ws->sk_partial ? 3 : 1;
     double best = 0.0;
-    int best_s = 0;
+    int best_s = -1;
     if (ms3)
         for (int c = 0; c < 3; ++c) ms3[c] = NAN;
     for (int c = 0; c < cands && e == hipSuccess && rc == FE_OK; ++c) {
@@ -463,9 +471,15 @@ int time_schedules(const double* H, int64_t n, int64_t ldh, double mu, double kT
         if (e == hipSuccess && rc == FE_OK) e = hipEventElapsedTime(&t, e0, e1);
         t_forced_schedule = -1;
         if (e != hipSuccess || rc != FE_OK) break;
+        // a candidate whose stream-K waits gave up (status FE_ERR_HIP from the trace reduction)
+        // produced no result: it is not timed and cannot be chosen
+        fe::Params pc;
+        e = hipMemcpy(&pc, ws->params, sizeof(pc), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) break;
+        if (pc.status == FE_ERR_HIP) continue;
         const double per = t / reps;
         if (ms3) ms3[c] = per;
-        if (c == 0 || per < best) {
+        if (best_s < 0 || per < best) {
             best = per;
             best_s = c;
         }
@@ -475,6 +489,7 @@ int time_schedules(const double* H, int64_t n, int64_t ldh, double mu, double kT
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     if (rc != FE_OK) return rc;
+    if (best_s < 0) return fail(FE_ERR_HIP, "autotune: no candidate schedule completed");
     if (best_out) *best_out = best_s;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (TunedEntry& t : g_tuned)
@@ -603,6 +618,37 @@ int fe_expand_entropy(const double* H, int64_t n, int64_t ldh, double mu, double
                          info, ws, static_cast<hipStream_t>(stream), 1);
 }
 
+int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, int32_t* geom,
+                        int32_t* segs, int32_t cap, int32_t* count) {
+    if (!geom || !count) return fail(FE_ERR_ARG, "geom and count are required");
+    if (schedule != 1 && schedule != 2) return fail(FE_ERR_ARG, "schedule must be 1 or 2");
+    const int tile = fe::split_tile_for(schedule);
+    if (np < tile || np % tile != 0 || np > (int64_t)1 << 20)
+        return fail(FE_ERR_ARG, "np must be a positive multiple of the schedule's tile");
+    if (grid < 1) return fail(FE_ERR_ARG, "grid must be >= 1");
+    if (segs && cap < 0) return fail(FE_ERR_ARG, "cap must be >= 0");
+    const fe::SkGeometry G = fe::split_sk_geometry(np, schedule, grid);
+    geom[0] = G.T; geom[1] = G.ntiles; geom[2] = G.nk; geom[3] = G.dp_tiles; geom[4] = G.groups;
+    geom[5] = G.grid;
+    *count = 0;
+    if (w < 0 || w >= G.grid) return FE_OK;
+    int k = 0;
+    fe::sk_walk(G, w, [&](int pass, int t, int kb0, int kb1, int jlo) {
+        if (segs && k < cap) {
+            int32_t* q = segs + 5 * k;
+            q[0] = pass; q[1] = t; q[2] = kb0; q[3] = kb1; q[4] = jlo;
+        }
+        ++k;
+    });
+    *count = k;
+    return FE_OK;
+}
+
+int fe_debug_streamk_giveup(int32_t enable) {
+    g_sk_giveup.store(enable ? 1 : 0);
+    return FE_OK;
+}
+
 int fe_sp2_coeffs(double mu_p, int32_t L, double* theta_out) {
     if (!theta_out || L < 1) return fail(FE_ERR_ARG, "bad arguments");
     if (!(mu_p > 0.0 && mu_p < 1.0)) return fail(FE_ERR_DOMAIN, "mu' must lie in (0, 1)");
@@ -627,3 +673,4 @@ double fe_layer_count(double beta_p) {
 }
 
 }  // extern "C"
+

@@ -112,19 +112,12 @@ inline int check_common(const double* H, int64_t n, int64_t ldh, double mu, doub
 }
 
 // Waits for the stream, copies the rescale parameters of workspace slot `which` into *info and
-// returns their status (stream-K wait failures are reported as FE_ERR_HIP).
+// returns their status (a stream-K wait that gave up is reported by the trace reduction as
+// FE_ERR_HIP).
 inline int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info* info) {
     FE_HIP(hipStreamSynchronize(s));
     fe::Params p;
     FE_HIP(hipMemcpy(&p, ws->params + which, sizeof(p), hipMemcpyDeviceToHost));
-    if (ws->sk_err) {
-        int err = 0;
-        FE_HIP(hipMemcpy(&err, ws->sk_err, sizeof(int), hipMemcpyDeviceToHost));
-        if (err) {
-            FE_HIP(hipMemset(ws->sk_err, 0, sizeof(int)));
-            return fail(FE_ERR_HIP, "a stream-K workgroup gave up waiting for a partial tile");
-        }
-    }
     info->emin = p.emin;
     info->emax = p.emax;
     info->mu_p = p.mu_p;
@@ -138,6 +131,9 @@ inline int read_info(fe_workspace* ws, int which, hipStream_t s, fe_rescale_info
     info->status = p.status;
     if (p.status == FE_ERR_DOMAIN) return fail(FE_ERR_DOMAIN, "mu lies outside the Gershgorin bounds of H");
     if (p.status == FE_ERR_NONFINITE) return fail(FE_ERR_NONFINITE, "H holds a non-finite entry");
+    if (p.status == FE_ERR_HIP)
+        return fail(FE_ERR_HIP, "a stream-K workgroup gave up waiting for a partial tile (the "
+                                "affected outputs are NaN)");
     return p.status;
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "fe.h"
+#include "streamk_plan.h"
 
 namespace fe {
 
@@ -103,9 +104,15 @@ struct SplitPlan {
     float* own;           // stream-K per-workgroup staging of finished tiles, grid x 256 x 256 floats
     uint32_t* flags;      // stream-K publication flags, one per workgroup (zero-initialised)
     uint32_t epoch;       // value written to a flag by this launch (distinct per launch)
+    uint32_t wait_epoch;  // value a waiting workgroup expects (= epoch; another value only to
+                          // exercise the give-up path from the host)
+    int spin_limit;       // sleeps before a wait gives up
     int* err;             // set to 1 if a bounded wait gave up
 };
 int split_tile_for(int streamk);
+// The stream-K plan the launcher uses for a padded size np, schedule 1 or 2, at most grid
+// workgroups (host; see streamk_plan.h).
+SkGeometry split_sk_geometry(int64_t np, int streamk, int grid);
 hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s);
 
 // Whole recursion for np <= 128 in FP64 inside one workgroup's LDS. The coefficients travel
@@ -244,8 +251,10 @@ hipError_t launch_dot(const void* D, int d_is_fp64, int64_t ldd, const double* A
                       const double* trD, const double* S, double* out, hipStream_t s);
 
 // Deterministic reduction of tile partials: out_tr = sum tr, out_sq = sum sq; if entropy,
-// out_S = 4 ln2 (sum tr - sum sq).
+// out_S = 4 ln2 (sum tr - sum sq). If err is set and *err != 0 (a stream-K wait gave up in this
+// expansion), the outputs are NaN, P->status becomes FE_ERR_HIP and *err is cleared.
 hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,
-                                  double* out_sq, double* out_S, const Params* P, hipStream_t s);
+                                  double* out_sq, double* out_S, Params* P, int* err,
+                                  hipStream_t s);
 
 }  // namespace fe

@@ -177,7 +177,8 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
     fin.out_mode = D ? (d_is_fp64 ? 1 : 0) : 2;
     fin.partials = ws->tparts;
     FE_HIP(fe::launch_combine(fin, s));
-    FE_HIP(fe::launch_reduce_partials(ws->tparts, fe::combine_tiles(np), trD, trD2, nullptr, P, s));
+    FE_HIP(fe::launch_reduce_partials(ws->tparts, fe::combine_tiles(np), trD, trD2, nullptr, P,
+                                      nullptr, s));
     if (info) return read_info(ws, 0, s, info);
     return FE_OK;
 }

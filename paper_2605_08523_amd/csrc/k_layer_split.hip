@@ -27,6 +27,7 @@
 //    A workgroup only ever waits for workgroups with smaller ids, which were dispatched earlier,
 //    and every wait is bounded.
 #include "split_common.h"
+#include "streamk_plan.h"
 
 namespace fe {
 namespace {
@@ -37,7 +38,6 @@ using CfgDP = Cfg<128, 2, 2, 64, 128, 1>;
 using CfgSK = Cfg<256, 2, 4, 32, 128, 2, 1>;   // direct-to-LDS operand staging
 using CfgSK2 = Cfg<128, 2, 2, 64, 128, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
 
-constexpr int kSpinLimit = 1 << 22;   // ~0.2 s of s_sleep before a wait gives up
 
 template <class C>
 __device__ inline void zero(Acc<C>& acc) {
@@ -67,15 +67,18 @@ k_layer_dp(LayerArgs p) {
 // Thread 0 waits until the workgroups of group g with indices jlo .. j-1 have published their
 // partials of the current tile (each publishes exactly once: a group never has more workgroups
 // than iterations, so every range is non-empty). Their ids g + NG jlo, ..., w - NG are all smaller
-// than w. Bounded: a wait that gives up sets *err. Ends with a barrier.
-__device__ inline void wait_published(const SplitPlan& sk, int g, int NG, int jlo, int w) {
+// than w. Bounded: a wait that gives up sets *err and returns true for the whole workgroup (the
+// caller's epilogue then writes NaN for the whole tile, so that no plausible value is built from
+// partials that may belong to an earlier layer). Ends with a barrier.
+__device__ inline bool wait_published(const SplitPlan& sk, int g, int NG, int jlo, int w) {
+    __shared__ int gave_up_all;
     if (threadIdx.x == 0) {
         bool gave_up = false;
         for (int wp = g + NG * jlo; wp < w && !gave_up; wp += NG) {
             int spins = 0;
             while (__hip_atomic_load(sk.flags + wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-                   sk.epoch) {
-                if (++spins > kSpinLimit) {
+                   sk.wait_epoch) {
+                if (++spins > sk.spin_limit) {
                     atomicOr(sk.err, 1);
                     gave_up = true;
                     break;
@@ -83,10 +86,12 @@ __device__ inline void wait_published(const SplitPlan& sk, int g, int NG, int jl
                 __builtin_amdgcn_s_sleep(2);
             }
         }
+        gave_up_all = gave_up ? 1 : 0;
     }
     // The partials are read after this barrier, i.e. after the flags were seen, with
     // device-coherent loads.
     __syncthreads();
+    return gave_up_all != 0;
 }
 
 template <bool BF, class C>
@@ -107,73 +112,48 @@ k_layer_sk(LayerArgs p, SplitPlan sk) {
     float* pub = sk.partial + (size_t)w * TILE;
     float* sY = reinterpret_cast<float*>(smem);
 
-    // Tiles [0, dp_tiles) were computed whole by a data-parallel launch before this one.
-    // The stream-K grid is split into NG groups (8 = one per XCD: the hardware hands workgroup
-    // w to XCD w % 8). Group g owns a contiguous block of the remaining tiles and runs stream-K
-    // over it with its GX workgroups, so a tile's contributors share one L2.
-    const int t0 = sk.dp_tiles, nsk = ntiles - sk.dp_tiles;
-    const int NG = sk.groups, g = w % NG, j = w / NG, GX = sk.grid / NG;
-    const int tg0 = t0 + (int)((int64_t)nsk * g / NG), tg1 = t0 + (int)((int64_t)nsk * (g + 1) / NG);
-    const int64_t base = (int64_t)tg0 * nk, total = (int64_t)(tg1 - tg0) * nk;
-    auto range_start = [&](int jj) { return base + total * jj / GX; };
-    const int64_t a_w = range_start(j), b_w = range_start(j + 1);
-
-    // Segments of [a_w, b_w), in three passes:
-    //  0: if the range stops inside its last tile, that tail segment, published first so that
-    //     the workgroup finishing that tile never waits behind this workgroup (no chains of
-    //     waits across the grid);
-    //  1: the segments that start on a tile boundary and finish their tile (no waiting);
-    //  2: if the range starts inside a tile, the rest of that tile, which waits for the earlier
-    //     workgroups' partials: last, so that they have had the longest time to publish.
-    const int t_last = (int)((b_w - 1) / nk);
-    const int64_t tail_start = (int64_t)t_last * nk > a_w ? (int64_t)t_last * nk : a_w;
-    const bool publishes = b_w < (int64_t)(t_last + 1) * nk;
-    const int64_t own_end = publishes ? tail_start : b_w;
-    const int64_t a_up = (a_w + nk - 1) / nk * nk;
-    const int64_t first_boundary = a_up < own_end ? a_up : own_end;
-    for (int pass = publishes ? 0 : 1; pass < 3; ++pass) {
-        int64_t it = pass == 0 ? tail_start : pass == 1 ? first_boundary : a_w;
-        const int64_t stop = pass == 0 ? b_w : pass == 1 ? own_end : first_boundary;
-        while (it < stop) {
-            const int t = (int)(it / nk);
-            const int kb0 = (int)(it - (int64_t)t * nk);
-            const int64_t rest = stop - it;
-            const int kb1 = (int)((int64_t)kb0 + rest < nk ? kb0 + rest : nk);
-            int I, J;
-            tile_coords(t, T, I, J);
-            // Earlier workgroups of the group with indices jlo .. j-1 hold the first kb0 blocks
-            // of this tile; their partial slots are NG tiles apart. The epilogue adds them in a
-            // fixed order, so the result does not depend on timing.
-            int jlo = j;
-            if (pass != 0 && kb0 > 0)
-                while (jlo > 0 && range_start(jlo) > (int64_t)t * nk) --jlo;
-            const float* parts = sk.partial + (size_t)(g + NG * jlo) * TILE;
-            Acc<C> acc;
-            zero(acc);
-            kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, kb0, kb1,
-                         acc, reinterpret_cast<uint16_t*>(smem));
-            if (pass == 0) {
-                // Publication: every wave waits until its device-coherent stores of the partial
-                // have completed, then one flag store (device-coherent too) announces the tile.
-                // No release fence: on this chip it writes back the whole L2, and the readers'
-                // acquire would invalidate it; the partial needs neither (see store_coherent).
-                store_tile<BF, C, true>(acc, pub);
-                __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
-                if (tid == 0)
-                    __hip_atomic_store(sk.flags + w, sk.epoch, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            } else if constexpr (kRegEpi) {
-                wait_published(sk, g, NG, jlo, w);
-                epilogue<BF, C, 1>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo);
-            } else {
-                store_tile<BF, C, false>(acc, own);
-                wait_published(sk, g, NG, jlo, w);
-                epilogue_mem<BF, C, 1>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t);
-            }
-            it += kb1 - kb0;
+    // Tiles [0, dp_tiles) were computed whole by a data-parallel launch before this one; the
+    // walk over the rest is in streamk_plan.h (shared with the host-side plan checks).
+    SkGeometry G;
+    G.T = T;
+    G.ntiles = ntiles;
+    G.nk = nk;
+    G.dp_tiles = sk.dp_tiles;
+    G.groups = sk.groups;
+    G.grid = sk.grid;
+    const int NG = sk.groups, g = w % NG, j = w / NG;
+    sk_walk(G, w, [&](int pass, int t, int kb0, int kb1, int jlo) {
+        int I, J;
+        tile_coords(t, T, I, J);
+        // Earlier workgroups of the group with indices jlo .. j-1 hold the first kb0 blocks of
+        // this tile; their partial slots are NG tiles apart. The epilogue adds them in a fixed
+        // order, so the result does not depend on timing.
+        const float* parts = sk.partial + (size_t)(g + NG * jlo) * TILE;
+        Acc<C> acc;
+        zero(acc);
+        kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, kb0, kb1, acc,
+                     reinterpret_cast<uint16_t*>(smem));
+        if (pass == 0) {
+            // Publication: every wave waits until its device-coherent stores of the partial
+            // have completed, then one flag store (device-coherent too) announces the tile.
+            // No release fence: on this chip it writes back the whole L2, and the readers'
+            // acquire would invalidate it; the partial needs neither (see store_coherent).
+            store_tile<BF, C, true>(acc, pub);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(sk.flags + w, sk.epoch, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else if constexpr (kRegEpi) {
+            const bool gave_up = wait_published(sk, g, NG, jlo, w);
+            epilogue<BF, C, 1>(p, acc, sY, I, J, t, parts, (size_t)NG * TILE, j - jlo, gave_up);
+        } else {
+            store_tile<BF, C, false>(acc, own);
+            const bool gave_up = wait_published(sk, g, NG, jlo, w);
+            epilogue_mem<BF, C, 1>(p, own, parts, (size_t)NG * TILE, j - jlo, sY, I, J, t,
+                                   gave_up);
         }
-    }
+    });
 }
 
 template <class K>
@@ -205,25 +185,15 @@ hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
     if (e != hipSuccess) return e;
     // One workgroup per CU, but never more workgroups per group than the group's (tile,
     // K-block) iterations: then every range is non-empty and each tile's earlier contributors
-    // all publish. Eight groups (one per XCD) when every XCD gets at least one tile and enough
-    // iterations, else one group over the whole grid.
-    const int64_t T = a.np / C::BM;
-    const int64_t ntiles = T * (T + 1) / 2, nk = a.np / C::BK;
-    SplitPlan plan = sk;
-    // With two or more full rounds of tiles, all but the last round run as whole tiles in a
-    // data-parallel launch first (their K walks stay in step, which the L2 rewards), and
-    // stream-K balances the last round plus the remainder. Configurations that stage their
-    // accumulators through memory run stream-K alone.
-    const int64_t rounds = ntiles / plan.grid;
+    // all publish (sk_plan). Configurations that stage their accumulators through memory run
+    // stream-K alone; the others run all but the last full round of tiles as whole tiles in a
+    // data-parallel launch first (their K walks stay in step, which the L2 rewards).
     constexpr bool reg_epi = C::MB * C::NB <= 4;
-    plan.dp_tiles = (reg_epi && rounds >= 2) ? (int)((rounds - 1) * plan.grid) : 0;
-    const int64_t nsk = ntiles - plan.dp_tiles;
-    if (nsk >= 8 && plan.grid % 8 == 0 && (nsk / 8) * nk >= plan.grid / 8) {
-        plan.groups = 8;
-    } else {
-        plan.groups = 1;
-        if (plan.grid > nsk * nk) plan.grid = (int)(nsk * nk);
-    }
+    const SkGeometry G = sk_plan(a.np, C::BM, C::BK, sk.grid, reg_epi);
+    SplitPlan plan = sk;
+    plan.grid = G.grid;
+    plan.groups = G.groups;
+    plan.dp_tiles = G.dp_tiles;
     if (plan.grid < 1) return hipErrorInvalidValue;
     if constexpr (reg_epi) {
         if (plan.dp_tiles > 0) {
@@ -244,6 +214,11 @@ hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
 
 int split_tile_for(int streamk) {
     return streamk == 1 ? CfgSK::BM : streamk == 2 ? CfgSK2::BM : CfgDP::BM;
+}
+
+SkGeometry split_sk_geometry(int64_t np, int streamk, int grid) {
+    if (streamk == 1) return sk_plan(np, CfgSK::BM, CfgSK::BK, grid, CfgSK::MB * CfgSK::NB <= 4);
+    return sk_plan(np, CfgSK2::BM, CfgSK2::BK, grid, CfgSK2::MB * CfgSK2::NB <= 4);
 }
 
 hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s) {

@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_rescale(RescaleArgs a) {
 
 __global__ void __launch_bounds__(256)
 k_reduce(const TracePartial* partials, int count, double* out_tr, double* out_sq, double* out_S,
-         const Params* P) {
+         Params* P, int* err) {
     // Fixed-order reduction: thread t sums partials t, t+256, ...; then a tree over threads.
     __shared__ double st[256], ss[256];
     double tr = 0.0, sq = 0.0;
@@ -224,6 +224,11 @@ k_reduce(const TracePartial* partials, int count, double* out_tr, double* out_sq
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        if (err && *err) {
+            // a stream-K wait gave up: the tiles it finished hold NaN; report it here too
+            *err = 0;
+            if (P->status >= 0) P->status = FE_ERR_HIP;
+        }
         const double bad = (P->status < 0) ? NAN : 0.0;
         if (out_tr) *out_tr = st[0] + bad;
         if (out_sq) *out_sq = ss[0] + bad;
@@ -280,9 +285,10 @@ hipError_t launch_fill_symmetric(double* H, int64_t n, uint64_t seed, hipStream_
 }
 
 hipError_t launch_reduce_partials(const TracePartial* partials, int count, double* out_tr,
-                                  double* out_sq, double* out_S, const Params* P, hipStream_t s) {
+                                  double* out_sq, double* out_S, Params* P, int* err,
+                                  hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, count, out_tr, out_sq, out_S,
-                       P);
+                       P, err);
     return hipGetLastError();
 }
 

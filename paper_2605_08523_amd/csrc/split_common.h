@@ -466,16 +466,21 @@ __device__ inline floatx4 load4_coherent(__amdgpu_buffer_rsrc_t rs, int off) {
 //   written to the tile and its mirror, or (entropy) U = A + X' traced only; FP64 trace sums
 //   accumulate in tr, sq. Diagonal tiles keep only the upper triangle of X and A, and their lower
 //   half of hi/lo (or D) comes from the mirror pass, so every stored matrix is exactly symmetric.
+//   poisoned: every output of the tile is NaN (a stream-K wait gave up).
 // Ends with a barrier (sY is free again).
 template <bool BF, class C, int UMAX>
 __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, int J,
                                  const float* __restrict__ Y0, const float* __restrict__ parts,
-                                 size_t part_stride, int nparts, double& tr, double& sq) {
+                                 size_t part_stride, int nparts, double& tr, double& sq,
+                                 bool poisoned) {
     const int tid = threadIdx.x;
     const int64_t np = p.np;
     const int64_t I0 = (int64_t)I * C::BM, J0 = (int64_t)J * C::BM;
     const bool diag = (I == J);
-    const float ca = p.a, cb = p.b, cc = p.c, dold = p.d_old, dnew = p.d_new;
+    // poisoned: the tile's partials could not be trusted (a stream-K wait gave up); a NaN weight
+    // makes every output of the tile NaN
+    const float ca = poisoned ? __builtin_nanf("") : p.a;
+    const float cb = p.b, cc = p.c, dold = p.d_old, dnew = p.d_new;
     const bool upd = dold != 0.0f || dnew != 0.0f;
     const bool last = p.last != 0;
     const bool ent = p.entropy != 0;
@@ -692,7 +697,7 @@ __device__ inline void write_traces(const LayerArgs& p, double tr, double sq, fl
 template <bool BF, class C, int UMAX = 8>
 __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY, int I, int J,
                                 int tile_index, const float* __restrict__ parts = nullptr,
-                                size_t part_stride = 0, int nparts = 0) {
+                                size_t part_stride = 0, int nparts = 0, bool poisoned = false) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / C::WN, wn = wave % C::WN;
     const float inv_s = BF ? 1.0f : (1.0f / 2048.0f);
@@ -717,7 +722,8 @@ __device__ inline void epilogue(const LayerArgs& p, const Acc<C>& acc, float* sY
             }
         }
         __syncthreads();
-        epi_chunk<BF, C, UMAX>(p, sY, R0, I, J, nullptr, parts, part_stride, nparts, tr, sq);
+        epi_chunk<BF, C, UMAX>(p, sY, R0, I, J, nullptr, parts, part_stride, nparts, tr, sq,
+                               poisoned);
     }
     if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
@@ -756,11 +762,13 @@ __device__ inline void store_tile(const Acc<C>& acc, float* __restrict__ dst) {
 template <bool BF, class C, int UMAX = 8>
 __device__ inline void epilogue_mem(const LayerArgs& p, const float* __restrict__ Y0,
                                     const float* __restrict__ parts, size_t part_stride,
-                                    int nparts, float* sY, int I, int J, int tile_index) {
+                                    int nparts, float* sY, int I, int J, int tile_index,
+                                    bool poisoned = false) {
     double tr = 0.0, sq = 0.0;
 #pragma unroll 1
     for (int ch = 0; ch < C::BM / C::EC; ++ch)
-        epi_chunk<BF, C, UMAX>(p, sY, ch * C::EC, I, J, Y0, parts, part_stride, nparts, tr, sq);
+        epi_chunk<BF, C, UMAX>(p, sY, ch * C::EC, I, J, Y0, parts, part_stride, nparts, tr, sq,
+                               poisoned);
     if (p.last) write_traces<C>(p, tr, sq, sY, tile_index);
 }
 
