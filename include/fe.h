@@ -112,6 +112,21 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
                       double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
                       void* stream);
 
+/* fe_expand_density without a workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation). It allocates
+ * nothing: its scratch (rescale parameters, partial sums and the padded matrices of one
+ * expansion) is a static device array of 66 MiB that the library holds on every GPU it runs on
+ * until the process ends. Limit: the padded matrices must fit 64 MiB, i.e. n <= 2048 for
+ * FE_PREC_FP16X2 / FE_PREC_BF16X2, n <= 2304 for FE_PREC_FP32, n <= 1664 for FE_PREC_FP64;
+ * larger n returns FE_ERR_WORKSPACE. Always the data-parallel schedule and the direct layer form.
+ * All calls on one GPU share that GPU's array: calls that overlap in time on one GPU (other
+ * streams or threads) race and must be serialised by the caller. Arguments, outputs and
+ * synchronisation as for fe_expand_density (H, D, trD, trD2 device; info host or NULL). */
+int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh, double mu, double kT,
+                              const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64,
+                              int64_t ldd, double* trD, double* trD2, fe_rescale_info* info,
+                              void* stream);
+
 /* Model-bank selection for one matrix: the bank model with the fewest layers whose region of
  * validity (Eq. conditions) holds the (beta', mu') of H at (mu, kT) (ties: the larger beta0); if
  * none does, the one with the widest region (an expansion with it clamps beta' and warns).

@@ -99,6 +99,8 @@ SIGNATURES = {
     "fe_embed_mlsp2": (_I32, [C.POINTER(fe_model), _I32, C.POINTER(_D)]),
     "fe_variant_eval": (_I32, [_P, _I32, C.POINTER(fe_qmodel), _P, _P, _P, _P, _P]),
     "fe_train_variant": (_I32, [_P, C.POINTER(fe_qmodel), C.POINTER(_D), _P, _P]),
+    "fe_expand_density_noalloc": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _P,
+                                         _I32, _I64, _P, _P, C.POINTER(fe_rescale_info), _P]),
     "fe_streamk_segments": (_I32, [_I64, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _I32,
                                    C.POINTER(_I32)]),
     "fe_debug_streamk_giveup": (_I32, [_I32]),
@@ -253,6 +255,31 @@ def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=Non
         d = info.as_dict()
         d["rc"] = rc
     return out, (tr[0] if traces else None), (tr[1] if traces else None), d
+
+
+def expand_density_noalloc(H, mu: float, kT: float, model, prec: str = "fp16x2", out=None,
+                           out_dtype=None, want_info: bool = False):
+    """fe_expand_density_noalloc (no workspace; the library's static scratch). Returns
+    (D, trD, trD2, info) as expand_density."""
+    import torch
+    n, ldh = _check_H(H)
+    mr = _model_of(model)
+    if out is None:
+        out = torch.empty((n, n), dtype=out_dtype or torch.float32, device=H.device)
+    if out.dtype not in (torch.float32, torch.float64) or out.stride(1) != 1:
+        raise TypeError("out must be a row-major float32/float64 device tensor")
+    tr = torch.empty(2, dtype=torch.float64, device=H.device)
+    info = fe_rescale_info() if want_info else None
+    rc = _check(lib().fe_expand_density_noalloc(
+        C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct), PREC[prec],
+        C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64), out.stride(0),
+        C.c_void_p(tr.data_ptr()), C.c_void_p(tr.data_ptr() + 8),
+        C.byref(info) if want_info else None, _stream_ptr()))
+    d = None
+    if want_info:
+        d = info.as_dict()
+        d["rc"] = rc
+    return out, tr[0], tr[1], d
 
 
 def expand_density_filling(H, n_occ: float, kT: float, model, prec: str = "fp16x2",

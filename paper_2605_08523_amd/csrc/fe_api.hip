@@ -109,10 +109,12 @@ WideBufs carve_wide(void* base, int64_t np, size_t elem) {
 
 // Runs Alg. 2 for one matrix on workspace slot `which`. alpha = 1 and entropy = 0 give the
 // density; entropy = 1 gives S (no matrix output).
+// noalloc: the caller cannot allocate (fe_expand_density_noalloc): the squared-affine form, whose
+// tables live on the heap, is not used.
 int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
                   int prec, double alpha, int entropy, void* D, int d_is_fp64, int64_t ldd,
                   double* trD, double* trD2, double* S, fe_rescale_info* info, fe_workspace* ws,
-                  hipStream_t s, int which) {
+                  hipStream_t s, int which, bool noalloc = false) {
     int rc = check_common(H, n, ldh, mu, kT, ws);
     if (rc) return rc;
     rc = check_model(m, entropy ? "entropy model" : "model");
@@ -175,13 +177,13 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         // squared-affine layers on request (FE_FORM=affine, FP16x2, coefficients permitting);
         // BF16x2 always keeps the FP32 state (its 16-bit split would carry the state alone)
         AffineForm af;
-        if (!bf && affine_allowed()) af = affine_form(m, alpha, dval);
+        if (!bf && !noalloc && affine_allowed()) af = affine_form(m, alpha, dval);
         ra.op_shift = af.ok ? af.op_shift : 0.0;
         FE_HIP(fe::launch_rescale(ra, s));
         const int T = (int)(np / tile);
         npart = T * (T + 1) / 2;
         if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
-        std::vector<float> d_old, d_new;
+        float d_old[kMaxLayers], d_new[kMaxLayers];
         pair_accumulator_terms(m->L, dval, d_old, d_new);
         for (int i = 0; i < m->L; ++i) {
             fe::LayerArgs la{};
@@ -674,3 +676,94 @@ double fe_layer_count(double beta_p) {
 
 }  // extern "C"
 
+// ---- the entry point that allocates nothing --------------------------------------------------
+//
+// fe_expand_density_noalloc keeps what fe_expand_density keeps in a workspace (rescale parameters,
+// Gershgorin and trace partials, and the padded matrices of one expansion) in `scratch`, a static
+// device array of fixed size: the loader places one copy on every GPU the library runs on, held
+// until the process ends. Host code never uses the array's name as an address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress on that GPU's first call and is kept per device.
+// Every call on a GPU shares that copy; nothing in it must start at zero (every buffer is written
+// before it is read within one call), and calls that overlap in time on one GPU race.
+
+namespace {
+
+constexpr size_t kNoAllocHeadBytes = (size_t)2 << 20;    // parameters and partials
+constexpr size_t kNoAllocSlotBytes = (size_t)64 << 20;   // the padded matrices of one expansion
+constexpr size_t kNoAllocParamsOff = 0;
+constexpr size_t kNoAllocBoundsOff = 256;
+constexpr size_t kNoAllocTracesOff =
+    kNoAllocBoundsOff + ((fe::kMaxBoundsBlocks * sizeof(fe::BoundsPartial) + 255) / 256) * 256;
+static_assert(2 * sizeof(fe::Params) <= kNoAllocBoundsOff, "parameter block");
+static_assert(kNoAllocTracesOff + (size_t)fe::kMaxTiles * sizeof(fe::TracePartial) <= kNoAllocHeadBytes,
+              "partials block");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocHeadBytes + kNoAllocSlotBytes];
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (the current device), looked up once per device.
+int noalloc_scratch(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(FE_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(FE_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_noalloc_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return FE_OK;
+}
+
+// Bytes of the padded matrices run_expansion carves from a slot for one density expansion of
+// size n in precision prec on the data-parallel schedule.
+size_t expansion_slot_bytes(int64_t n, int prec) {
+    if (prec == FE_PREC_FP64 && round_up(n, 16) <= fe::small_f64_max_np()) {
+        const size_t np = (size_t)round_up(n, 16);
+        return 3 * np * np * sizeof(double);
+    }
+    if (prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2) {
+        const size_t np = (size_t)round_up(n, fe::split_tile_for(0));
+        return 2 * np * np * sizeof(float) + 4 * np * np * sizeof(uint16_t);
+    }
+    const size_t np = (size_t)round_up(n, fe::wide_tile());
+    return 3 * np * np * (prec == FE_PREC_FP64 ? sizeof(double) : sizeof(float));
+}
+
+}  // namespace
+
+extern "C" int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh, double mu,
+                                         double kT, const fe_model* m, int32_t prec, void* D,
+                                         int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                                         fe_rescale_info* info, void* stream) {
+    if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
+    if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X2) return fail(FE_ERR_ARG, "unknown precision");
+    if (n > ((int64_t)1 << 16) || expansion_slot_bytes(n, prec) > kNoAllocSlotBytes)
+        return fail(FE_ERR_WORKSPACE, "n exceeds the no-allocation scratch (64 MiB of matrices: "
+                                      "n <= 2048 for FP16X2/BF16X2, 2304 for FP32, 1664 for FP64)");
+    int dev = 0;
+    FE_HIP(hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    int rc = noalloc_scratch(dev, &base);
+    if (rc) return rc;
+    // a workspace view of the static scratch: no stream-K buffers (data-parallel schedule), one slot
+    fe_workspace w;
+    w.device = dev;
+    w.max_n = n;
+    w.np_cap = (int64_t)1 << 40;   // the size check above replaces the slot-capacity check
+    w.slot_bytes = kNoAllocSlotBytes;
+    w.slot[0] = base + kNoAllocHeadBytes;
+    w.params = reinterpret_cast<fe::Params*>(base + kNoAllocParamsOff);
+    w.bparts = reinterpret_cast<fe::BoundsPartial*>(base + kNoAllocBoundsOff);
+    w.tparts = reinterpret_cast<fe::TracePartial*>(base + kNoAllocTracesOff);
+    return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
+                         info, &w, static_cast<hipStream_t>(stream), 0, true);
+}

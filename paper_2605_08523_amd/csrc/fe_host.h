@@ -266,9 +266,8 @@ inline AffineForm affine_form(const fe_model* m, double alpha, DV dv) {
 // write A.
 // dv(j) is d_j after the skip rule; d_old[i], d_new[i] are layer i's weights of X_i, X_{i+1}.
 template <class DV>
-inline void pair_accumulator_terms(int L, DV dv, std::vector<float>& d_old, std::vector<float>& d_new) {
-    d_old.assign(L, 0.0f);
-    d_new.assign(L, 0.0f);
+inline void pair_accumulator_terms(int L, DV dv, float* d_old, float* d_new) {
+    for (int i = 0; i < L; ++i) d_old[i] = d_new[i] = 0.0f;
     for (int j = 1; j < L;) {
         if (dv(j) == 0.0) {
             ++j;
@@ -278,6 +277,12 @@ inline void pair_accumulator_terms(int L, DV dv, std::vector<float>& d_old, std:
         if (j + 1 < L) d_new[j] = (float)dv(j + 1);
         j += 2;
     }
+}
+template <class DV>
+inline void pair_accumulator_terms(int L, DV dv, std::vector<float>& d_old, std::vector<float>& d_new) {
+    d_old.assign(L, 0.0f);
+    d_new.assign(L, 0.0f);
+    pair_accumulator_terms(L, dv, d_old.data(), d_new.data());
 }
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
