@@ -38,6 +38,9 @@ BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_m
         "mlsp2_L18_b150_mu0p5", "mlsp2_L19_b200_mu0p5", "mlsp2_L20_b300_mu0p5",
         "mlsp2_L22_b600_mu0p5", "mlsp2_L24_b1500_mu0p5", "mlsp2_L27_b3000_mu0p5",
         "mlsp2_L29_b4000_mu0p5", "mlsp2_L36_b1e4_mu0p5"]
+# trained entropy models (theta_entropy, Sec. III.B), selected per matrix by the same rule
+ENTROPY_BANK = ["entropy_L26_b40_mu1third", "entropy_L26_b1500_mu1third", "entropy_L40_b1e4_mu1third"]
+LARGE_ORACLE = os.path.join(ROOT, "tests", "golden", "large16384_oracle.npz")
 
 
 def parse():
@@ -93,6 +96,7 @@ def timed(fn, steps, warmup, torch):
 KERNEL_SOURCES = ("fe_api.hip", "fe_internal.h", "k_layer_split.hip", "split_common.h")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_counters_anderson4096.md")
 SQ_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_sq_counters_anderson4096.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "k_layer_split_anderson4096_fp16x2.md")
 
 
 def _profile_record(path, tag):
@@ -118,11 +122,35 @@ def measured_traffic():
     return rec["bytes_per_launch"] if rec else None
 
 
+def measured_profile():
+    """The rocprofv3 kernel-trace average of the layer kernel and the event figure of the same
+    session, from the committed summary (None if the layer kernel's sources changed since)."""
+    rec = _profile_record(TRACE_SUMMARY, "trace_json")
+    return rec
+
+
 def measured_pipe_busy():
     """Clock and MFMA-pipe occupancy of the layer kernel from the committed SQ-counter summary
     (None if stale)."""
     rec = _profile_record(SQ_SUMMARY, "sq_json")
     return {k: rec[k] for k in ("clock_ghz", "mfma_pipe_busy", "vendor_gemm_mfma_pipe_busy")} if rec else None
+
+
+def layer_event_ms(api, expand, torch, reps=10):
+    """Duration of each layer launch of the split path, from HIP events the library records on the
+    launch stream around every layer launch (fe_debug_layer_events), over `reps` expansions."""
+    expand()
+    torch.cuda.synchronize()
+    api.layer_events(True)
+    per = []
+    try:
+        for _ in range(reps):
+            expand()
+            per.extend(api.layer_events_read().tolist())
+    finally:
+        api.layer_events(False)
+    per.sort()
+    return {"mean": sum(per) / len(per), "median": per[len(per) // 2], "launches": len(per)}
 
 
 def main():
@@ -205,7 +233,9 @@ def main():
         for _ in range(args.warmup + args.steps):
             step()
         torch.cuda.synchronize()
-        print("profile run done", flush=True)
+        lay = layer_event_ms(api, expand, torch)
+        print(f"profile run done; layer launch (HIP events, this process): mean {lay['mean']:.4f} "
+              f"ms over {lay['launches']} launches, model {m.name}", flush=True)
         return
 
     ms = timed(step, args.steps, args.warmup, torch)
@@ -223,9 +253,13 @@ def main():
     ms_expand = timed(expand, args.steps, args.warmup, torch) if bank is not None else ms
     ms1 = timed(step1, args.steps, args.warmup, torch)
     L = m.L
-    layer_ms = (ms_expand - ms1) / (L - 1)
+    layer_ms_diff = (ms_expand - ms1) / (L - 1)
+    lay = layer_event_ms(api, expand, torch)
+    layer_ms = lay["mean"]
     flop_layer = 2.0 * n ** 3                         # algorithmic X^2 of one layer
-    tile = 128 if n <= 8192 else 256
+    # executed MFMA work: three products on the upper tiles of the schedule the tuner chose
+    sched = api.autotune_lookup(n, prec=args.prec, ws=ws)
+    tile = 256 if sched == "sk256" else 128
     T = -(-n // tile)
     np_ = T * tile
     exec_flop_layer = 3 * 2.0 * (T * (T + 1) // 2) * tile * tile * np_   # three MFMA products, upper tiles
@@ -265,20 +299,31 @@ def main():
             "executed_mfma_tflops": exec_flop_layer / (layer_ms * 1e-3) / 1e12,
             "executed_frac": exec_flop_layer / (layer_ms * 1e-3) / 1e12 / peak,
             "sq_counters": measured_pipe_busy(),
-            "method": f"HIP events on the launch stream: (t(L={L}) - t(L=1)) / {L - 1}",
+            "schedule": sched,
+            "method": (f"HIP events recorded by the library on the launch stream around each of the "
+                       f"{L} layer launches of an expansion, mean over {lay['launches']} launches "
+                       f"(median {lay['median']:.4f} ms); by differencing expansions, "
+                       f"(t(L={L}) - t(L=1)) / {L - 1} = {layer_ms_diff:.4f} ms"),
+            "layer_ms_by_differencing": layer_ms_diff,
+            "profile": measured_profile(),
         },
         "prologue_plus_one_layer_ms": ms1,
         "autotune": tuned,
         "ms_per_step_median": per_ms[len(per_ms) // 2],
         "ms_per_step_p90": per_ms[int(0.9 * (len(per_ms) - 1))],
     }
-    # the whole single-matrix path of Alg. 2: density and entropy (theta_fermi reused for S,
-    # alpha = 0.842704, as in the paper's Table I rows with theta_fermi)
-    ms_ds = timed(lambda: (step(), api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec,
-                                                      ws=ws)),
+    # the whole single-matrix path of Alg. 2: density and entropy, the entropy with the trained
+    # entropy coefficients (theta_entropy) selected for this matrix like the density model
+    ebank = [models.load(x) for x in ENTROPY_BANK]
+    ebank_refs = [api.make_model(x.theta, x.beta0, x.mu0) for x in ebank]
+    ke = api.select_model(Hd, mu, kT, ebank_refs, ws=ws)
+    ment, mentref = ebank[ke], ebank_refs[ke]
+    ms_ds = timed(lambda: (step(), api.expand_entropy(Hd, mu, kT, mentref, ment.alpha,
+                                                      prec=args.prec, ws=ws)),
                   args.steps, args.warmup, torch)
     out["step_with_entropy"] = {"ms": ms_ds, "per_s": 1000.0 / ms_ds,
-                                "what": "model selection + density + entropy expansion"}
+                                "entropy_model": ment.name,
+                                "what": "model selection + density + entropy expansion (theta_entropy)"}
     if bank is not None:
         out["expand_only_ms"] = ms_expand
         m26 = models.load("mlsp2_L26_b1500_mu1third")
@@ -301,6 +346,19 @@ def main():
         out["affine_form"] = {"ms_per_step": ms_aff, "value": 1000.0 / ms_aff,
                               "what": "FE_FORM=affine: operand = shifted state, no FP32 state "
                                       "traffic in the epilogue"}
+    # the final correction layer (last product by FP32 MFMA, FP64 epilogue, float64 D), opt-in
+    D64 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    ms_corr = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D64, ws=ws,
+                                               final_correction=True), args.steps, args.warmup,
+                    torch)
+    api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D64, ws=ws, final_correction=True)
+    torch.cuda.synchronize()
+    Dcorr = D64.cpu().numpy()
+    del D64
+    out["final_correction"] = {"ms_expand": ms_corr, "ms_expand_without": ms_expand,
+                               "what": "final_correction=1: last layer X^2 by FP32 MFMA from the "
+                                       "FP32 state, D = A + d X + (a X^2 + b X + c I) in FP64, "
+                                       "float64 D"}
     # the timed runs end with the one-layer model: recompute D with the full model for the error
     _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws,
                                             want_info=True)
@@ -366,15 +424,23 @@ def main():
                                          "eigendecomposition + V f V^T assembly in FP64 (numpy); "
                                          "median of 3 runs"}
         err = Dg - ref["D"]
-        S_gpu = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
+        S_gpu = float(api.expand_entropy(Hd, mu, kT, mentref, ment.alpha, prec=args.prec,
+                                         ws=ws)[0])
+        S_fermi = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
         out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
                                   "max_abs": float(np.max(np.abs(err))),
                                   "norm2": norm2_sym(err, torch, dev),
                                   "abs_dTrD": abs(float(trD) - ref["trD"]),
                                   "abs_dTrD2": abs(float(trD2) - ref["trD2"]),
-                                  "abs_dS": abs(S_gpu - ref["S"]), "S": ref["S"]}
+                                  "abs_dS": abs(S_gpu - ref["S"]), "S": ref["S"],
+                                  "entropy_model": ment.name,
+                                  "abs_dS_theta_fermi_reused": abs(S_fermi - ref["S"])}
         if Daff is not None:
             out["affine_form"]["fro_over_N_vs_oracle"] = float(np.linalg.norm(Daff - ref["D"]) / n)
+        ec = Dcorr - ref["D"]
+        out["final_correction"]["error_vs_oracle"] = {
+            "fro_over_N": float(np.linalg.norm(ec) / n), "max_abs": float(np.max(np.abs(ec))),
+            "norm2": norm2_sym(ec, torch, dev)}
     print(json.dumps(out), flush=True)
 
 
@@ -449,11 +515,11 @@ def bench_batch(args, torch, api, models, workloads, dev):
 
 def bench_large(args, torch, api, models, workloads, dev):
     """One N = 16384 solve (h_ij = g_ij exp(-|i-j|/32), on-site U[-1,1], kT = 0.02, mu at 40%
-    filling), the 40-layer (1e4, 1/3) model: density (FP16x2) and entropy (FP16x2, theta_fermi
-    reused, alpha = 0.842704). mu is the midpoint of eigenvalues 0.4N and 0.4N + 1 (GPU
-    eigvalsh; input generation). Checked against the FP64 expansion on the GPU (the oracle's
-    eigendecomposition would take tens of minutes at this size). Also timed with the model the
-    bank selects for the matrix (`model_bank`)."""
+    filling), the 40-layer (1e4, 1/3) model: density (FP16x2) and entropy (FP16x2, the trained
+    40-layer entropy model; theta_fermi reused at alpha = 0.842704 beside it). mu is the oracle's
+    40%-filling value from its stored reference for this input (tests/golden), against which the
+    result is checked (sampled rows, probe products, traces, S), as well as against the FP64
+    expansion on the GPU. Also timed with the model the bank selects (`model_bank`)."""
     import numpy as np
     m = models.load("mlsp2_L40_b1e4_mu1third")
     t0 = time.perf_counter()
@@ -461,9 +527,17 @@ def bench_large(args, torch, api, models, workloads, dev):
     n = c["H"].shape[0]
     Hd = torch.from_numpy(c["H"]).to(dev)
     del c["H"]
-    lam = torch.linalg.eigvalsh(Hd).cpu().numpy()
-    k = int(0.4 * n)
-    mu, kT = float(0.5 * (lam[k - 1] + lam[k])), c["kT"]
+    # the oracle's reference for this seeded input (stored by tests/golden/make_large16384.py, which
+    # calls only the oracle): its 40%-filling mu, eigenvalues, Tr D, sum D^2, S, sampled rows of D
+    # and D v for probe vectors
+    ref = np.load(LARGE_ORACLE) if os.path.exists(LARGE_ORACLE) else None
+    kT = c["kT"]
+    if ref is not None:
+        mu = float(ref["mu"])
+    else:
+        lam = torch.linalg.eigvalsh(Hd).cpu().numpy()
+        k = int(0.4 * n)
+        mu = float(0.5 * (lam[k - 1] + lam[k]))
     print(f"large input generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ws = api.Workspace(n)
     D = torch.empty((n, n), dtype=torch.float32, device=dev)
@@ -474,9 +548,30 @@ def bench_large(args, torch, api, models, workloads, dev):
     steps = max(1, min(args.steps, 5))
     ms = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec=args.prec, out=D, ws=ws),
                steps, 1, torch)
-    ms_s = timed(lambda: api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws),
+    ment = models.load("entropy_L40_b1e4_mu1third")
+    mentref = api.make_model(ment.theta, ment.beta0, ment.mu0)
+    ms_s = timed(lambda: api.expand_entropy(Hd, mu, kT, mentref, ment.alpha, prec=args.prec, ws=ws),
                  steps, 1, torch)
+    S_ent = float(api.expand_entropy(Hd, mu, kT, mentref, ment.alpha, prec=args.prec, ws=ws)[0])
     S = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec=args.prec, ws=ws)[0])
+    oracle_err = None
+    if ref is not None:
+        pfx = "mlsp2_L40_b1e4_mu1third"
+        dv = (D.double() @ torch.from_numpy(ref["V"]).to(dev)).cpu().numpy()
+        rows = D[torch.from_numpy(ref["rows"]).to(dev)].double().cpu().numpy()
+        oracle_err = {
+            "rows_max_abs_vs_exact": float(np.max(np.abs(rows - ref["exact_rows"]))),
+            "probes_rel_vs_exact": float(np.linalg.norm(dv - ref["exact_probes"])
+                                         / np.linalg.norm(ref["exact_probes"])),
+            "abs_dTrD_vs_exact": abs(float(trD) - float(ref["exact_trD"])),
+            "abs_dTrD_vs_recursion": abs(float(trD) - float(ref[f"{pfx}_trD"])),
+            "abs_dS_theta_entropy_vs_exact": abs(S_ent - float(ref["exact_S"])),
+            "abs_dS_theta_entropy_vs_recursion": abs(S_ent - float(ref["entropy_L40_b1e4_mu1third_S"]))
+            if "entropy_L40_b1e4_mu1third_S" in ref.files else None,
+            "abs_dS_theta_fermi_reused_vs_exact": abs(S - float(ref["exact_S"])),
+            "S_exact": float(ref["exact_S"]),
+            "sample": "the oracle's stored reference (tests/golden/large16384_oracle.npz): "
+                      "8 rows of D, D v for 4 probe vectors, Tr D, S"}
     D64, trD64, _, _ = api.expand_density(Hd, mu, kT, mref, prec="fp64", ws=ws,
                                           out_dtype=torch.float64, want_info=True)
     S64 = float(api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec="fp64", ws=ws)[0])
@@ -507,8 +602,9 @@ def bench_large(args, torch, api, models, workloads, dev):
                       "schedule": api.autotune_lookup(n, args.prec, ws)},
            "autotune": tuned,
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
-           "entropy_ms": ms_s,
+           "entropy_ms": ms_s, "entropy_model": ment.name,
            "trD": float(trD), "trD_target": 0.4 * n,
+           "error_vs_oracle": oracle_err,
            "vs_fp64_expansion": {"fro_over_N": float(torch.linalg.norm(err).item() / n),
                                  "max_abs": float(err.abs().max().item()),
                                  "norm2": norm2_sym(err, torch, dev),
@@ -601,6 +697,11 @@ def bench_train(args, torch, api, models, workloads, dev):
     from paper_2605_08523_amd import training
     L, beta0, mu0 = 40, 1e4, 1.0 / 3.0
     torch.cuda.synchronize()
+    # iterations until the sample points' max error is below 1e-7 (the paper: "a few hundred"
+    # with geodesic acceleration, Sec. III.C)
+    t0 = time.perf_counter()
+    _, rep7, ok7 = training.train_coeffs(L, beta0, mu0, n_points=8192, max_iter=10000, tol=1e-7)
+    dt7 = time.perf_counter() - t0
     t0 = time.perf_counter()
     th, rep, ok = training.train_coeffs(L, beta0, mu0, n_points=8192, max_iter=10000, tol=1e-10)
     dt = time.perf_counter() - t0
@@ -611,7 +712,9 @@ def bench_train(args, torch, api, models, workloads, dev):
                       "mu0": mu0, "points": 8192},
            "iterations": rep["iters"], "seconds_to_stop": dt,
            "ms_per_iteration": 1e3 * dt / max(1, rep["iters"]), "converged": bool(ok),
-           "max_error_grid": rep["max_err_grid"]}
+           "max_error_grid": rep["max_err_grid"],
+           "to_1e-7": {"iterations": rep7["iters"], "seconds": dt7, "reached": bool(ok7),
+                       "max_error_grid": rep7["max_err_grid"]}}
     # matrix-level passes
     n, nm, kT = 256, 64, 0.1
     model = api.make_model(th, beta0, mu0)
@@ -641,6 +744,21 @@ def bench_train(args, torch, api, models, workloads, dev):
                              "ms_per_matrix": ms_mb / nm, "loss": loss0,
                              "rms_error": float(np.sqrt(loss0 / (nm * n * n))),
                              "grad_norm": float(theta.grad.norm())}
+    # the fit refined on the 64 matrices (fe_train_coeffs with the matrix set: combined objective,
+    # matrix term through the FP32 forward / backward kernels), from the fitted coefficients
+    mats = [(X0, Dr.contiguous()) for X0, Dr in zip(X0s, refs)]
+    t0 = time.perf_counter()
+    thm, repm, _ = training.train_coeffs(L, beta0, mu0, n_points=8192, max_iter=1, tol=1e-10,
+                                         theta_init=th, mats=mats, mat_iters=10, mat_weight=1.0)
+    dtm = time.perf_counter() - t0
+    out["matrix_set_refinement"] = {
+        "matrices": nm, "N": n, "iterations": repm["mat_iters"], "kept": repm["mat_accepted"],
+        "seconds": dtm, "matrix_loss_start": repm["mat_loss_start"],
+        "matrix_loss_end": repm["mat_loss_end"],
+        "grid_max_error_before": rep["max_err_grid"],
+        "grid_max_error_after": repm["max_err_grid"],
+        "what": "loss = sum_m ||P(X0_m) - Dref_m||_F^2, P by the FP32 kernels; Dref from FP64 "
+                "eigendecompositions on the GPU; weight 1 against the 8192 points' squares"}
     print(json.dumps(out), flush=True)
 
 

@@ -103,14 +103,21 @@ int fe_rescale(const double* H, int64_t n, int64_t ldh, double mu, double kT, co
                float* X0, int64_t ldx, fe_rescale_info* info, fe_workspace* ws, void* stream);
 
 /* Density matrix by Alg. 2 (steps 1-4) with model m in precision prec (FE_PREC_*).
+ * final_correction: 0 or 1. With 1 and a 16-bit split precision, the last layer is a correction
+ *    layer: its product X^2 comes from the FP32 copy of the state by FP32 MFMA (FP32 inputs and
+ *    accumulation) instead of the 16-bit split, and its output D = A + d X + (a X^2 + b X + c I)
+ *    (I - D if flipped) is formed in FP64; a float64 D then receives these FP64 values. The
+ *    correction layer costs one FP32 matrix product (2 N^3 at the FP32 MFMA rate). Ignored for
+ *    FE_PREC_FP32 and FE_PREC_FP64 (their layers are already FP32 / FP64 throughout).
  * D: device, n x n (ld ldd), float32 if d_is_fp64 == 0 else float64; exactly symmetric.
- *    In the 16-bit and FP32 modes D carries FP32 values (also when stored as float64).
+ *    Without the correction layer, the 16-bit and FP32 modes give FP32 values (also when D is
+ *    float64).
  * trD, trD2: device float64 scalars or NULL: Tr D and sum_ij D_ij^2 accumulated in FP64.
  * info: as for fe_rescale (synchronizes when non-NULL). */
 int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double kT,
-                      const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64, int64_t ldd,
-                      double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
-                      void* stream);
+                      const fe_model* m, int32_t prec, int32_t final_correction, void* D,
+                      int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                      fe_rescale_info* info, fe_workspace* ws, void* stream);
 
 /* fe_expand_density without a workspace, for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid allocation). It allocates
@@ -121,11 +128,12 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
  * larger n returns FE_ERR_WORKSPACE. Always the data-parallel schedule and the direct layer form.
  * All calls on one GPU share that GPU's array: calls that overlap in time on one GPU (other
  * streams or threads) race and must be serialised by the caller. Arguments, outputs and
- * synchronisation as for fe_expand_density (H, D, trD, trD2 device; info host or NULL). */
+ * synchronisation as for fe_expand_density (H, D, trD, trD2 device; info host or NULL),
+ * final_correction included. */
 int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh, double mu, double kT,
-                              const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64,
-                              int64_t ldd, double* trD, double* trD2, fe_rescale_info* info,
-                              void* stream);
+                              const fe_model* m, int32_t prec, int32_t final_correction, void* D,
+                              int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                              fe_rescale_info* info, void* stream);
 
 /* Model-bank selection for one matrix: the bank model with the fewest layers whose region of
  * validity (Eq. conditions) holds the (beta', mu') of H at (mu, kT) (ties: the larger beta0); if
@@ -261,6 +269,21 @@ typedef struct {
     int32_t sampling;     /* FE_SAMPLE_* */
     int32_t max_iter;     /* Levenberg-Marquardt iterations */
     double tol;           /* stop when max |model - target| over the points is below tol */
+    /* Optional matrix set (Fermi target only; n_mats = 0 for none): after the fit on the points,
+     * the coefficients are refined on F = sum_k r_k^2 / 2 + (mat_weight / 2) sum_m
+     * ||P(X0_m) - Dref_m||_F^2, P the recursion of the layers evaluated on the matrix by the FP32
+     * kernels of fe_matrix_forward / fe_matrix_backward (Sec. III.C trains on numbers; the matrix
+     * term trains on the same function at the matrices' own spectra). Each refinement step is a
+     * damped Gauss-Newton step whose metric is the points' J^T J and whose gradient holds both
+     * terms; it is kept when F decreases. */
+    int32_t n_mats;               /* number of training matrices */
+    int32_t mat_iters;            /* refinement iterations (>= 1 when n_mats > 0) */
+    int64_t mat_n;                /* their size, a multiple of 64 */
+    const float* const* X0s;      /* host array of n_mats device pointers: X0 in the model
+                                     coordinate (FP32, mat_n x mat_n, symmetric) */
+    const double* const* Drefs;   /* host array of n_mats device pointers: the target density in
+                                     the same coordinate, g(X0) (FP64, mat_n x mat_n) */
+    double mat_weight;            /* weight of the matrix term (> 0) */
 } fe_train_spec;
 
 typedef struct {
@@ -269,6 +292,10 @@ typedef struct {
     double max_err_points;  /* max |residual| over the sample points */
     double max_err_grid;    /* max |model - target| on 200001 uniform points of [0, 1], FP64 */
     double lambda;          /* final damping */
+    int32_t mat_iters;      /* matrix-set refinement: iterations run, */
+    int32_t mat_accepted;   /*   steps kept, */
+    double mat_loss_start;  /*   sum_m ||P(X0_m) - Dref_m||_F^2 before and */
+    double mat_loss_end;    /*   after the refinement (FP32 kernels, FP64 sums) */
 } fe_train_report;
 
 /* Fit the coefficients by Levenberg-Marquardt with geodesic acceleration (Sec. III.C). Starts
@@ -286,6 +313,13 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
  * d theta_{i,c}. theta is host L x 4 (L <= 96). Asynchronous. */
 int fe_scalar_eval(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
                    double mu0, double alpha, const double* tgt, double* r, double* JT, void* stream);
+
+/* Second directional derivative of the scalar model along a coefficient direction, the input of
+ * the trainer's geodesic acceleration (Sec. III.C): r2[k] = d^2/dt^2 model(y_k; theta + t v) at
+ * t = 0, exact (forward mode of second order, FP64). y, r2: device, n points; v: device L x 4
+ * (the layout of theta); theta: host L x 4 (L <= 96). Asynchronous. */
+int fe_scalar_second(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
+                     double mu0, double alpha, const double* v, double* r2, void* stream);
 
 /* FP32 matrix recursion for fitting on matrices: hist is device float32 (L+1) x n x n with
  * hist[0] = X0 (symmetric, model coordinate) on entry; layer i writes X_{i+1} into hist[i+1]
@@ -400,7 +434,7 @@ int fe_variant_eval(const double* y, int32_t n, const fe_qmodel* m, const double
                     const double* tgt, double* r, double* JT, void* stream);
 
 /* Fit a Skip-SP2 or Max-SP2 model to the Fermi target of spec (spec->target must be
- * FE_TARGET_FERMI; spec->L is ignored) by the same Levenberg-Marquardt iteration as
+ * FE_TARGET_FERMI and spec->n_mats 0; spec->L is ignored) by the same Levenberg-Marquardt iteration as
  * fe_train_coeffs, starting from init (shape and host coefficients; the embedding of a trained
  * MLSP2 model, fe_embed_mlsp2, is the intended start, App. C). coef_out (host) receives the
  * best coefficients. Synchronizes; allocates its own device scratch for the call. */
@@ -439,6 +473,15 @@ int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, i
  * as a wait that timed out would. Every kernel still exits normally; the tiles finished after a
  * give-up are NaN, the traces NaN, and the rescale info status FE_ERR_HIP. */
 int fe_debug_streamk_giveup(int32_t enable);
+
+/* Per-launch timing of the layer kernel with HIP events on the call's stream (process-wide; for
+ * the roofline measurement of Sec. V.A's layer product): while enabled, every expansion on the
+ * 16-bit split path records an event before its first layer launch and one after each layer
+ * launch. fe_debug_layer_events_read waits for the most recent call's last event and writes the
+ * elapsed time of each of its layer launches, in ms, to ms[0 .. min(count, cap) - 1] (host);
+ * count (host) receives the number of layers timed. Enabling or disabling clears the record. */
+int fe_debug_layer_events(int32_t enable);
+int fe_debug_layer_events_read(double* ms, int32_t cap, int32_t* count);
 
 /* Message for the last error on the calling thread (static storage, never NULL). */
 const char* fe_last_error(void);

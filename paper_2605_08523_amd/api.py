@@ -66,8 +66,8 @@ SIGNATURES = {
     "fe_workspace_destroy": (_I32, [_P]),
     "fe_rescale": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _P, _I64,
                           C.POINTER(fe_rescale_info), _P, _P]),
-    "fe_expand_density": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _P, _I32, _I64,
-                                 _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
+    "fe_expand_density": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _I32, _P, _I32,
+                                 _I64, _P, _P, C.POINTER(fe_rescale_info), _P, _P]),
     "fe_expand_density_filling": (_I32, [_P, _I64, _I64, _D, _D, _D, C.POINTER(fe_model), _I32, _D,
                                          _I32, _P, _I32, _I64, _P, _P, C.POINTER(_D),
                                          C.POINTER(_I32), C.POINTER(fe_rescale_info), _P, _P]),
@@ -81,6 +81,7 @@ SIGNATURES = {
     "fe_sp2_coeffs": (_I32, [_D, _I32, C.POINTER(_D)]),
     "fe_train_coeffs": (_I32, [_P, _P, _P, _P, _P, _P]),
     "fe_scalar_eval": (_I32, [_P, _I32, _P, _I32, _I32, _D, _D, _P, _P, _P, _P]),
+    "fe_scalar_second": (_I32, [_P, _I32, _P, _I32, _I32, _D, _D, _P, _P, _P]),
     "fe_matrix_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
     "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
@@ -99,11 +100,13 @@ SIGNATURES = {
     "fe_embed_mlsp2": (_I32, [C.POINTER(fe_model), _I32, C.POINTER(_D)]),
     "fe_variant_eval": (_I32, [_P, _I32, C.POINTER(fe_qmodel), _P, _P, _P, _P, _P]),
     "fe_train_variant": (_I32, [_P, C.POINTER(fe_qmodel), C.POINTER(_D), _P, _P]),
-    "fe_expand_density_noalloc": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _P,
-                                         _I32, _I64, _P, _P, C.POINTER(fe_rescale_info), _P]),
+    "fe_expand_density_noalloc": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, _I32,
+                                         _P, _I32, _I64, _P, _P, C.POINTER(fe_rescale_info), _P]),
     "fe_streamk_segments": (_I32, [_I64, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _I32,
                                    C.POINTER(_I32)]),
     "fe_debug_streamk_giveup": (_I32, [_I32]),
+    "fe_debug_layer_events": (_I32, [_I32]),
+    "fe_debug_layer_events_read": (_I32, [C.POINTER(_D), _I32, C.POINTER(_I32)]),
     "fe_last_error": (C.c_char_p, []),
     "fe_version": (C.c_char_p, []),
 }
@@ -230,7 +233,7 @@ def rescale(H, mu: float, kT: float, model, want_X0: bool = True, ws: Workspace 
 
 def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=None,
                    out_dtype=None, want_info: bool = False, traces: bool = True,
-                   ws: Workspace | None = None):
+                   ws: Workspace | None = None, final_correction: bool = False):
     """fe_expand_density. Returns (D, trD, trD2, info): D a tensor (float32 unless out_dtype or
     ``out`` says float64), trD/trD2 0-d float64 device tensors (or None), info a dict or None.
     Asynchronous on the current stream unless want_info."""
@@ -246,7 +249,8 @@ def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=Non
     info = fe_rescale_info() if want_info else None
     rc = _check(lib().fe_expand_density(
         C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct), PREC[prec],
-        C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64), out.stride(0),
+        int(bool(final_correction)), C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64),
+        out.stride(0),
         C.c_void_p(tr.data_ptr() if traces else 0),
         C.c_void_p(tr.data_ptr() + 8 if traces else 0),
         C.byref(info) if want_info else None, ws.handle, _stream_ptr()))
@@ -258,7 +262,7 @@ def expand_density(H, mu: float, kT: float, model, prec: str = "fp16x2", out=Non
 
 
 def expand_density_noalloc(H, mu: float, kT: float, model, prec: str = "fp16x2", out=None,
-                           out_dtype=None, want_info: bool = False):
+                           out_dtype=None, want_info: bool = False, final_correction: bool = False):
     """fe_expand_density_noalloc (no workspace; the library's static scratch). Returns
     (D, trD, trD2, info) as expand_density."""
     import torch
@@ -272,7 +276,8 @@ def expand_density_noalloc(H, mu: float, kT: float, model, prec: str = "fp16x2",
     info = fe_rescale_info() if want_info else None
     rc = _check(lib().fe_expand_density_noalloc(
         C.c_void_p(H.data_ptr()), n, ldh, float(mu), float(kT), C.byref(mr.struct), PREC[prec],
-        C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64), out.stride(0),
+        int(bool(final_correction)), C.c_void_p(out.data_ptr()), int(out.dtype == torch.float64),
+        out.stride(0),
         C.c_void_p(tr.data_ptr()), C.c_void_p(tr.data_ptr() + 8),
         C.byref(info) if want_info else None, _stream_ptr()))
     d = None
@@ -456,6 +461,21 @@ def streamk_segments(np_: int, schedule: int, grid: int, w: int):
                                      C.byref(cnt)))
     g = dict(zip(("T", "ntiles", "nk", "dp_tiles", "groups", "grid"), list(geom)))
     return g, segs[:cnt.value]
+
+
+def layer_events(enable: bool) -> None:
+    """fe_debug_layer_events: time each layer launch of the split path with HIP events."""
+    _check(lib().fe_debug_layer_events(1 if enable else 0))
+
+
+def layer_events_read():
+    """fe_debug_layer_events_read: ms per layer launch of the most recent expansion (numpy)."""
+    cnt = C.c_int32()
+    _check(lib().fe_debug_layer_events_read(None, 0, C.byref(cnt)))
+    out = np.zeros(max(cnt.value, 1))
+    _check(lib().fe_debug_layer_events_read(out.ctypes.data_as(C.POINTER(C.c_double)), cnt.value,
+                                            C.byref(cnt)))
+    return out[:cnt.value]
 
 
 def debug_streamk_giveup(enable: bool) -> None:

@@ -44,6 +44,24 @@ std::mutex g_tune_mu;
 std::vector<TunedEntry> g_tuned;
 // fe_debug_streamk_giveup: stream-K waits expect a flag value that is never written
 std::atomic<int> g_sk_giveup{0};
+// fe_debug_layer_events: HIP events around each layer launch of the split path (the last call's)
+std::mutex g_ev_mu;
+bool g_ev_on = false;
+std::vector<hipEvent_t> g_ev;
+int g_ev_used = 0;
+
+// Event k of the layer timing pool (created on first use), or nullptr if timing is off.
+hipEvent_t layer_event(int k) {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    if (!g_ev_on) return nullptr;
+    while ((int)g_ev.size() <= k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_ev.push_back(e);
+    }
+    if (k + 1 > g_ev_used) g_ev_used = k + 1;
+    return g_ev[k];
+}
 constexpr uint32_t kNeverEpoch = 0xFFFFFFFFu;   // no launch publishes this value
 thread_local int t_forced_schedule = -1;   // set by the tuner around its timing runs
 
@@ -111,10 +129,14 @@ WideBufs carve_wide(void* base, int64_t np, size_t elem) {
 // density; entropy = 1 gives S (no matrix output).
 // noalloc: the caller cannot allocate (fe_expand_density_noalloc): the squared-affine form, whose
 // tables live on the heap, is not used.
+// final_correction (16-bit modes): the last layer is a correction layer, its product X^2 from the
+// FP32 state by FP32 MFMA and its epilogue D = A + d X + (a X^2 + b X + c I) in FP64, written
+// without rounding to FP32 when D is float64.
 int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT, const fe_model* m,
                   int prec, double alpha, int entropy, void* D, int d_is_fp64, int64_t ldd,
                   double* trD, double* trD2, double* S, fe_rescale_info* info, fe_workspace* ws,
-                  hipStream_t s, int which, bool noalloc = false) {
+                  hipStream_t s, int which, bool noalloc = false,
+                  bool final_correction = false) {
     int rc = check_common(H, n, ldh, mu, kT, ws);
     if (rc) return rc;
     rc = check_model(m, entropy ? "entropy model" : "model");
@@ -176,8 +198,9 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         ra.mode = 0; ra.bf16 = bf;
         // squared-affine layers on request (FE_FORM=affine, FP16x2, coefficients permitting);
         // BF16x2 always keeps the FP32 state (its 16-bit split would carry the state alone)
+        const bool corr = final_correction;
         AffineForm af;
-        if (!bf && !noalloc && affine_allowed()) af = affine_form(m, alpha, dval);
+        if (!bf && !noalloc && !corr && affine_allowed()) af = affine_form(m, alpha, dval);
         ra.op_shift = af.ok ? af.op_shift : 0.0;
         FE_HIP(fe::launch_rescale(ra, s));
         const int T = (int)(np / tile);
@@ -185,7 +208,13 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
         float d_old[kMaxLayers], d_new[kMaxLayers];
         pair_accumulator_terms(m->L, dval, d_old, d_new);
-        for (int i = 0; i < m->L; ++i) {
+        const int nsplit = corr ? m->L - 1 : m->L;   // layers on the 16-bit split
+        if (hipEvent_t ev = layer_event(0)) {
+            std::lock_guard<std::mutex> lk(g_ev_mu);
+            g_ev_used = 1;
+            FE_HIP(hipEventRecord(ev, s));
+        }
+        for (int i = 0; i < nsplit; ++i) {
             fe::LayerArgs la{};
             la.np = np; la.n = n;
             la.hi_in = b.hi[i & 1]; la.lo_in = b.lo[i & 1];
@@ -213,6 +242,25 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
                 plan.spin_limit = giveup ? 64 : (1 << 22);   // 1 << 22: ~0.2 s of sleeps
             }
             FE_HIP(fe::launch_layer_split(la, bf, plan, s));
+            if (hipEvent_t ev = layer_event(i + 1)) FE_HIP(hipEventRecord(ev, s));
+        }
+        if (corr) {
+            // the correction layer: the FP32 state X_{L-1} (upper triangle maintained by the
+            // split layers) is mirrored to full, then one FP32 MFMA layer with the FP64 epilogue
+            const int i = m->L - 1;
+            FE_HIP(fe::launch_mirror_upper_f32(b.X, np, s));
+            fe::WideArgs wa{};
+            wa.np = np; wa.n = n;
+            wa.X_in = b.X; wa.X_out = nullptr; wa.A = b.A;
+            wa.a = th[4 * i]; wa.b = th[4 * i + 1]; wa.c = th[4 * i + 2]; wa.d_next = 0.0;
+            wa.last = 1; wa.out_mode = out_mode; wa.entropy = entropy; wa.D = D; wa.ldd = ldd;
+            wa.P = P; wa.partials = tp;
+            wa.f64_epi = 1;
+            wa.d_last = d_old[i];
+            const int Tw = (int)(np / fe::wide_tile());
+            npart = Tw * (Tw + 1) / 2;
+            if (npart > fe::kMaxTiles) return fail(FE_ERR_WORKSPACE, "too many tiles");
+            FE_HIP(fe::launch_layer_f32(wa, s));
         }
     } else {
         // FP64 beyond the one-workgroup size, or FP32: 64 x 64 tiled MFMA layers on X itself
@@ -350,11 +398,14 @@ int fe_rescale(const double* H, int64_t n, int64_t ldh, double mu, double kT, co
 }
 
 int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double kT,
-                      const fe_model* m, int32_t prec, void* D, int32_t d_is_fp64, int64_t ldd,
-                      double* trD, double* trD2, fe_rescale_info* info, fe_workspace* ws,
-                      void* stream) {
+                      const fe_model* m, int32_t prec, int32_t final_correction, void* D,
+                      int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                      fe_rescale_info* info, fe_workspace* ws, void* stream) {
+    if (final_correction != 0 && final_correction != 1)
+        return fail(FE_ERR_ARG, "final_correction must be 0 or 1");
+    const bool corr = final_correction && (prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2);
     return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
-                         info, ws, static_cast<hipStream_t>(stream), 0);
+                         info, ws, static_cast<hipStream_t>(stream), 0, false, corr);
 }
 
 int fe_expand_density_filling(const double* H, int64_t n, int64_t ldh, double n_occ, double kT,
@@ -646,6 +697,27 @@ int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, i
     return FE_OK;
 }
 
+int fe_debug_layer_events(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    g_ev_on = enable != 0;
+    g_ev_used = 0;
+    return FE_OK;
+}
+
+int fe_debug_layer_events_read(double* ms, int32_t cap, int32_t* count) {
+    if (!count) return fail(FE_ERR_ARG, "count is NULL");
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    *count = g_ev_used > 1 ? g_ev_used - 1 : 0;
+    if (*count == 0 || !ms) return FE_OK;
+    FE_HIP(hipEventSynchronize(g_ev[g_ev_used - 1]));
+    for (int k = 0; k + 1 < g_ev_used && k < cap; ++k) {
+        float t = 0.0f;
+        FE_HIP(hipEventElapsedTime(&t, g_ev[k], g_ev[k + 1]));
+        ms[k] = t;
+    }
+    return FE_OK;
+}
+
 int fe_debug_streamk_giveup(int32_t enable) {
     g_sk_giveup.store(enable ? 1 : 0);
     return FE_OK;
@@ -741,10 +813,13 @@ size_t expansion_slot_bytes(int64_t n, int prec) {
 }  // namespace
 
 extern "C" int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh, double mu,
-                                         double kT, const fe_model* m, int32_t prec, void* D,
-                                         int32_t d_is_fp64, int64_t ldd, double* trD, double* trD2,
+                                         double kT, const fe_model* m, int32_t prec,
+                                         int32_t final_correction, void* D, int32_t d_is_fp64,
+                                         int64_t ldd, double* trD, double* trD2,
                                          fe_rescale_info* info, void* stream) {
     if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
+    if (final_correction != 0 && final_correction != 1)
+        return fail(FE_ERR_ARG, "final_correction must be 0 or 1");
     if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X2) return fail(FE_ERR_ARG, "unknown precision");
     if (n > ((int64_t)1 << 16) || expansion_slot_bytes(n, prec) > kNoAllocSlotBytes)
         return fail(FE_ERR_WORKSPACE, "n exceeds the no-allocation scratch (64 MiB of matrices: "
@@ -764,6 +839,7 @@ extern "C" int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh
     w.params = reinterpret_cast<fe::Params*>(base + kNoAllocParamsOff);
     w.bparts = reinterpret_cast<fe::BoundsPartial*>(base + kNoAllocBoundsOff);
     w.tparts = reinterpret_cast<fe::TracePartial*>(base + kNoAllocTracesOff);
+    const bool corr = final_correction && (prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2);
     return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
-                         info, &w, static_cast<hipStream_t>(stream), 0, true);
+                         info, &w, static_cast<hipStream_t>(stream), 0, true, corr);
 }

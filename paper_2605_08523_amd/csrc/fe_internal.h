@@ -151,8 +151,12 @@ struct WideArgs {
     const Params* P;
     TracePartial* partials;
     int plain;
+    int f64_epi;            // last layer of the FP32 kernel as a correction layer: FP64 epilogue,
+    double d_last;          //   D = A + d_last X + (a Y + b X + c I) in FP64, not rounded to FP32
 };
 int wide_tile();
+// X[i][j] = X[j][i] for i > j (np x np FP32, np a multiple of wide_tile()).
+hipError_t launch_mirror_upper_f32(float* X, int64_t np, hipStream_t s);
 hipError_t launch_layer_f32(const WideArgs& a, hipStream_t s);
 hipError_t launch_layer_f64(const WideArgs& a, hipStream_t s);
 
@@ -217,6 +221,8 @@ struct ScalarArgs {
     const double* tgt;      // target values or NULL (residual = model)
     double* r;              // out: model - target, n
     double* JT;             // out (or NULL): Jacobian transposed, 4L x n
+    const double* vdir;     // device 4L direction v (read when r2 is set)
+    double* r2;             // out (or NULL): second directional derivative of the model along v
     int n, L, target;       // target 0: Fermi, 1: entropy
     double mu0, alpha;
     double theta[4 * kScalarMaxL];
@@ -239,6 +245,10 @@ struct BwdArgs {
     double* part;           // per-block partial sums, nblocks x 4
 };
 hipError_t launch_bwd_elem(const BwdArgs& a, int nblocks, double* grad4, hipStream_t s);
+// G = P - Dref (FP32; G may be NULL) and *sumsq = sum (P - Dref)^2 in FP64 over `total` entries
+// (nblocks partial sums in part, reduced in a fixed order).
+hipError_t launch_mat_residual(const float* P, const double* Dref, int64_t total, float* G,
+                               double* part, int nblocks, double* sumsq, hipStream_t s);
 hipError_t launch_fwd_out(const float* hist, int64_t n, int L, const MatTheta& th, float* P,
                           hipStream_t s);
 

@@ -5,10 +5,12 @@
 // g(y) = 1/(1 + exp(beta0 (mu0 - y))) or to its entropy function on the model coordinate
 // y in [0, 1], by Levenberg-Marquardt (Marquardt damping scaled by the running maximum of the
 // Gram diagonal) with geodesic acceleration (Transtrum and Sethna): the second directional
-// derivative of the residuals along the step is estimated by a central difference and its
-// correction is kept only when it is small against the step. Residuals and the Jacobian are
+// derivative of the residuals along the step is computed exactly (forward mode of second order in
+// the residual kernel; a central difference for the Skip-SP2 / Max-SP2 models) and its
+// correction is kept only when 2 |a| <= 0.75 |step|. Residuals and the Jacobian are
 // evaluated on the GPU in FP64 (one lane per sample point), J^T J and J^T r on the GPU, the
-// damped normal equations are solved on the host in FP64 (Cholesky).
+// damped normal equations are solved on the host in FP64 (Cholesky). The damping follows Nielsen's
+// update (gain ratio of actual to predicted cost reduction).
 #include <math.h>
 #include <string.h>
 
@@ -19,6 +21,12 @@
 #include "fe_variant.h"
 
 using namespace fehost;
+
+extern "C" int fe_matrix_forward(float* hist, int64_t n, const double* theta, int32_t L, float* P,
+                                 void* stream);
+extern "C" int fe_matrix_backward(const float* hist, int64_t n, const double* theta, int32_t L,
+                                  const float* G, float* work, double* part, int32_t nblocks,
+                                  double* grad, void* stream);
 
 namespace {
 
@@ -128,11 +136,14 @@ struct DevBufs {
 
 // Levenberg-Marquardt with geodesic acceleration over P coefficients and n residuals (see the
 // file comment). launch(th, jac) enqueues the residuals at th into d.r and, if jac, the Jacobian
-// transposed into d.JT, on stream s. On return th holds the best coefficients, r their
+// transposed into d.JT, on stream s. If second is given (has_second), second(th, v) enqueues the
+// exact second directional derivative of the residuals along v into d.v; otherwise it is
+// estimated by a central difference. On return th holds the best coefficients, r their
 // residuals (host), and it / lam the iterations and final damping.
-template <class Launch>
+template <class Launch, class Second>
 hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r, DevBufs& d,
-                  hipStream_t s, int max_iter, double tol, Launch launch, int& it, double& lam) {
+                  hipStream_t s, int max_iter, double tol, Launch launch, bool has_second,
+                  Second second, int& it, double& lam) {
     std::vector<double> rp(n), rm(n), G((size_t)P * P), g(P), Gl((size_t)P * P), dmax(P, 0.0);
     auto eval = [&](const std::vector<double>& t, std::vector<double>& out, bool jac) -> hipError_t {
         hipError_t err = launch(t, jac);
@@ -140,10 +151,14 @@ hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r,
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         return err;
     };
-    auto gram = [&](bool full, const std::vector<double>* v, std::vector<double>& gout) -> hipError_t {
+    // J^T v for v on the host (copied to d.v), or already in d.v (v_on_device), or r (neither)
+    auto gram = [&](bool full, const std::vector<double>* v, std::vector<double>& gout,
+                    bool v_on_device = false) -> hipError_t {
         hipError_t err = hipSuccess;
         if (v) err = hipMemcpyAsync(d.v, v->data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess) err = fe::launch_gram(d.JT, v ? d.v : d.r, P, n, full ? d.G : nullptr, d.g, s);
+        if (err == hipSuccess)
+            err = fe::launch_gram(d.JT, (v || v_on_device) ? d.v : d.r, P, n, full ? d.G : nullptr,
+                                  d.g, s);
         if (err == hipSuccess && full) err = hipMemcpyAsync(G.data(), d.G, sizeof(double) * P * P, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipMemcpyAsync(gout.data(), d.g, sizeof(double) * P, hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
@@ -161,6 +176,7 @@ hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r,
     };
 
     lam = 1e-3;
+    double nu = 2.0;
     it = 0;
     hipError_t e = eval(th, r, true);
     double C = cost(r);
@@ -184,21 +200,30 @@ hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r,
         Gl = G;
         for (int p = 0; p < P; ++p) Gl[(size_t)p * P + p] += lam * dmax[p];
         if (!cholesky(Gl, P)) {
-            lam *= 4.0;
+            lam *= nu;
+            nu *= 2.0;
             continue;
         }
         for (int p = 0; p < P; ++p) dl[p] = -g[p];
         chol_solve(Gl, P, dl);
-        // geodesic acceleration: r'' along dl by a central difference with step h
-        const double h = 0.1;
-        for (int p = 0; p < P; ++p) tn[p] = th[p] + h * dl[p];
-        e = eval(tn, rp, false);
-        if (e != hipSuccess) break;
-        for (int p = 0; p < P; ++p) tn[p] = th[p] - h * dl[p];
-        e = eval(tn, rm, false);
-        if (e != hipSuccess) break;
-        for (int k = 0; k < n; ++k) rm[k] = (rp[k] - 2.0 * r[k] + rm[k]) / (h * h);
-        e = gram(false, &rm, tmp);
+        // geodesic acceleration (Transtrum and Sethna): the second directional derivative r''
+        // of the residuals along dl, a = -(J^T J + lam D)^-1 J^T r'', step dl + a / 2, kept only
+        // when 2 |a| / |dl| <= 0.75
+        if (has_second) {
+            e = second(th, dl);
+            if (e != hipSuccess) break;
+            e = gram(false, nullptr, tmp, true);
+        } else {
+            const double h = 0.1;
+            for (int p = 0; p < P; ++p) tn[p] = th[p] + h * dl[p];
+            e = eval(tn, rp, false);
+            if (e != hipSuccess) break;
+            for (int p = 0; p < P; ++p) tn[p] = th[p] - h * dl[p];
+            e = eval(tn, rm, false);
+            if (e != hipSuccess) break;
+            for (int k = 0; k < n; ++k) rm[k] = (rp[k] - 2.0 * r[k] + rm[k]) / (h * h);
+            e = gram(false, &rm, tmp);
+        }
         if (e != hipSuccess) break;
         for (int p = 0; p < P; ++p) acc[p] = -tmp[p];
         chol_solve(Gl, P, acc);
@@ -207,8 +232,9 @@ hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r,
             na += acc[p] * acc[p];
             nd += dl[p] * dl[p];
         }
-        if (sqrt(na) > 0.75 * sqrt(nd)) {
-            lam *= 2.0;
+        if (2.0 * sqrt(na) > 0.75 * sqrt(nd)) {
+            lam *= nu;
+            nu *= 2.0;
             if (lam > 1e14) break;
             continue;
         }
@@ -217,18 +243,156 @@ hipError_t lm_run(int P, int n, std::vector<double>& th, std::vector<double>& r,
         if (e != hipSuccess) break;
         const double Cn = cost(rp);
         if (Cn < C) {
+            // gain ratio against the reduction the linearised residuals predict for the velocity,
+            // pred = -g.dl - dl.G.dl / 2; damping update of Nielsen (as used by Transtrum and
+            // Sethna): lam *= max(1/3, 1 - (2 rho - 1)^3) on acceptance, doubling factors after
+            // each rejection
+            double pred = 0.0;
+            for (int p = 0; p < P; ++p) {
+                double gd = 0.0;
+                for (int q = 0; q < P; ++q) gd += G[(size_t)p * P + q] * dl[q];
+                pred -= g[p] * dl[p] + 0.5 * dl[p] * gd;
+            }
+            const double rho = pred > 0.0 ? (C - Cn) / pred : 1.0;
+            const double t = 2.0 * rho - 1.0;
+            lam = std::max(lam * std::max(1.0 / 3.0, 1.0 - t * t * t), 1e-15);
+            nu = 2.0;
             th = tn;
             r = rp;
             C = Cn;
-            lam = std::max(lam / 3.0, 1e-15);
             have_gram = false;   // J at the new point is already on the device
         } else {
-            lam *= 2.0;
+            lam *= nu;
+            nu *= 2.0;
             if (lam > 1e14) break;
             e = eval(th, r, true);   // restore J at the current point
         }
     }
     return e;
+}
+
+// Refinement of the coefficients on a set of matrices (fe_train_spec's matrix set): damped
+// Gauss-Newton steps on F = C_points + (w/2) sum_m ||P(X0_m) - Dref_m||_F^2 whose metric is the
+// points' J^T J (scaled by the running Gram diagonal, as in the fit) and whose gradient holds both
+// terms (the matrix term's from the FP32 backward pass); a step is kept when F decreases. th and
+// r (the points' residuals) are updated in place.
+template <class Launch>
+int matrix_refine(const fe_train_spec* sp, int P, int n, std::vector<double>& th,
+                  std::vector<double>& r, DevBufs& d, hipStream_t s, Launch launch, int& its,
+                  int& accepted, double& loss0, double& loss1) {
+    const int L = sp->L;
+    const int64_t nm = sp->mat_n;
+    const size_t nn = (size_t)nm * nm;
+    const int nb = 256;
+    float *hist = nullptr, *Pd = nullptr, *Gm = nullptr, *work = nullptr;
+    double *part = nullptr, *gradd = nullptr, *ssq = nullptr;
+    auto release = [&]() {
+        for (void* q : {(void*)hist, (void*)Pd, (void*)Gm, (void*)work, (void*)part, (void*)gradd,
+                        (void*)ssq})
+            if (q) (void)hipFree(q);
+    };
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&hist), sizeof(float) * (L + 1) * nn);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&Pd), sizeof(float) * nn);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&Gm), sizeof(float) * nn);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&work), sizeof(float) * 3 * nn);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&part), sizeof(double) * 4 * nb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&gradd), sizeof(double) * P);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ssq), sizeof(double));
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(e, "matrix refinement scratch");
+    }
+    // sum_m ||P(X0_m) - Dref_m||^2 at t and, if gm, its half-gradient sum_m J_m^T r_m
+    auto mat_eval = [&](const std::vector<double>& t, double& loss, std::vector<double>* gm) -> int {
+        loss = 0.0;
+        if (gm) gm->assign(P, 0.0);
+        std::vector<double> gh(P);
+        for (int m = 0; m < sp->n_mats; ++m) {
+            FE_HIP(hipMemcpyAsync(hist, sp->X0s[m], sizeof(float) * nn, hipMemcpyDeviceToDevice, s));
+            int rc = fe_matrix_forward(hist, nm, t.data(), L, Pd, s);
+            if (rc) return rc;
+            FE_HIP(fe::launch_mat_residual(Pd, sp->Drefs[m], (int64_t)nn, gm ? Gm : nullptr, part, nb,
+                                           ssq, s));
+            double v = 0.0;
+            FE_HIP(hipMemcpyAsync(&v, ssq, sizeof(double), hipMemcpyDeviceToHost, s));
+            if (gm) {
+                rc = fe_matrix_backward(hist, nm, t.data(), L, Gm, work, part, nb, gradd, s);
+                if (rc) return rc;
+                FE_HIP(hipMemcpyAsync(gh.data(), gradd, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+            }
+            FE_HIP(hipStreamSynchronize(s));
+            loss += v;
+            if (gm)
+                for (int p = 0; p < P; ++p) (*gm)[p] += gh[p];
+        }
+        return FE_OK;
+    };
+    auto points = [&](const std::vector<double>& t, std::vector<double>& out, bool jac) -> int {
+        FE_HIP(launch(t, jac));
+        FE_HIP(hipMemcpyAsync(out.data(), d.r, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        FE_HIP(hipStreamSynchronize(s));
+        return FE_OK;
+    };
+    const double w = sp->mat_weight;
+    std::vector<double> G((size_t)P * P), g(P), gm(P), Gl((size_t)P * P), dl(P), tn(P), rn(n);
+    std::vector<double> dmax(P, 0.0);
+    double lm_ = 0.0;
+    int rc = points(th, r, true);
+    if (!rc) rc = mat_eval(th, lm_, &gm);
+    loss0 = lm_;
+    double lam = 1e-3;
+    its = accepted = 0;
+    bool fresh = true;   // J, G, g and gm belong to th
+    for (; rc == FE_OK && its < sp->mat_iters; ++its) {
+        if (fresh) {
+            FE_HIP(fe::launch_gram(d.JT, d.r, P, n, d.G, d.g, s));
+            FE_HIP(hipMemcpyAsync(G.data(), d.G, sizeof(double) * P * P, hipMemcpyDeviceToHost, s));
+            FE_HIP(hipMemcpyAsync(g.data(), d.g, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+            FE_HIP(hipStreamSynchronize(s));
+            for (int p = 0; p < P; ++p)
+                for (int q = 0; q < p; ++q) G[(size_t)p * P + q] = G[(size_t)q * P + p];
+            double big = 0.0;
+            for (int p = 0; p < P; ++p) {
+                dmax[p] = std::max(dmax[p], G[(size_t)p * P + p]);
+                big = std::max(big, dmax[p]);
+            }
+            for (int p = 0; p < P; ++p) dmax[p] = std::max(dmax[p], 1e-12 * big);
+            fresh = false;
+        }
+        double C = 0.0;
+        for (double v : r) C += 0.5 * v * v;
+        const double F = C + 0.5 * w * lm_;
+        Gl = G;
+        for (int p = 0; p < P; ++p) Gl[(size_t)p * P + p] += lam * dmax[p];
+        if (!cholesky(Gl, P)) {
+            lam *= 4.0;
+            continue;
+        }
+        for (int p = 0; p < P; ++p) dl[p] = -(g[p] + w * gm[p]);
+        chol_solve(Gl, P, dl);
+        for (int p = 0; p < P; ++p) tn[p] = th[p] + dl[p];
+        rc = points(tn, rn, false);
+        double lmn = 0.0;
+        if (!rc) rc = mat_eval(tn, lmn, nullptr);
+        if (rc) break;
+        double Cn = 0.0;
+        for (double v : rn) Cn += 0.5 * v * v;
+        if (Cn + 0.5 * w * lmn < F) {
+            th = tn;
+            ++accepted;
+            lam = std::max(lam / 3.0, 1e-15);
+            rc = points(th, r, true);
+            if (!rc) rc = mat_eval(th, lm_, &gm);
+            fresh = true;
+        } else {
+            lam *= 2.0;
+            if (lam > 1e14) break;
+        }
+    }
+    loss1 = lm_;
+    if (!fresh && rc == FE_OK) rc = points(th, r, false);
+    release();
+    return rc;
 }
 
 // Device scratch of one fit: n points, P coefficients (with an optional coefficient buffer).
@@ -262,6 +426,19 @@ int fe_scalar_eval(const double* y, int32_t n, const double* theta, int32_t L, i
     return FE_OK;
 }
 
+int fe_scalar_second(const double* y, int32_t n, const double* theta, int32_t L, int32_t target,
+                     double mu0, double alpha, const double* v, double* r2, void* stream) {
+    if (!y || !r2 || !theta || !v || n < 1) return fail(FE_ERR_ARG, "bad arguments");
+    if (L < 1 || L > fe::scalar_max_layers()) return fail(FE_ERR_ARG, "L out of range for the scalar kernel");
+    if (target != FE_TARGET_FERMI && target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
+    fe::ScalarArgs a{};
+    a.y = y; a.tgt = nullptr; a.r = nullptr; a.JT = nullptr; a.vdir = v; a.r2 = r2;
+    a.n = n; a.L = L; a.target = target; a.mu0 = mu0; a.alpha = alpha;
+    memcpy(a.theta, theta, sizeof(double) * 4 * L);
+    FE_HIP(fe::launch_scalar_eval(a, static_cast<hipStream_t>(stream)));
+    return FE_OK;
+}
+
 int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double* theta_out,
                     fe_train_report* rep, fe_workspace* ws, void* stream) {
     (void)ws;
@@ -271,6 +448,16 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
     if (n < P) return fail(FE_ERR_ARG, "need at least 4L sample points");
     if (!(spec->beta0 > 0.0) || !(spec->mu0 > 0.0 && spec->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
     if (spec->target != FE_TARGET_FERMI && spec->target != FE_TARGET_ENTROPY) return fail(FE_ERR_ARG, "unknown target");
+    if (spec->n_mats < 0) return fail(FE_ERR_ARG, "n_mats must be >= 0");
+    if (spec->n_mats > 0) {
+        if (spec->target != FE_TARGET_FERMI) return fail(FE_ERR_ARG, "the matrix set takes the Fermi target");
+        if (!spec->X0s || !spec->Drefs) return fail(FE_ERR_ARG, "X0s and Drefs are required with n_mats > 0");
+        if (spec->mat_n < 64 || spec->mat_n % 64 != 0) return fail(FE_ERR_ARG, "mat_n must be a positive multiple of 64");
+        if (spec->mat_iters < 1) return fail(FE_ERR_ARG, "mat_iters must be >= 1");
+        if (!(spec->mat_weight > 0.0) || !isfinite(spec->mat_weight)) return fail(FE_ERR_ARG, "mat_weight must be positive");
+        for (int m = 0; m < spec->n_mats; ++m)
+            if (!spec->X0s[m] || !spec->Drefs[m]) return fail(FE_ERR_ARG, "a matrix pointer is NULL");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double b0 = spec->beta0, m0 = spec->mu0;
     const double alpha = spec->target == FE_TARGET_ENTROPY ? spec->alpha : 1.0;
@@ -308,14 +495,40 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
         memcpy(sa.theta, t.data(), sizeof(double) * P);
         sa.r = d.r;
         sa.JT = jac ? d.JT : nullptr;
+        sa.r2 = nullptr;
         return fe::launch_scalar_eval(sa, s);
+    };
+    // exact r'' along v: forward mode of second order in the residual kernel, into d.v (d.r keeps
+    // the residuals of the current point)
+    auto second = [&](const std::vector<double>& t, const std::vector<double>& v) -> hipError_t {
+        hipError_t err = hipMemcpyAsync(d.coef, v.data(), sizeof(double) * P, hipMemcpyHostToDevice, s);
+        if (err != hipSuccess) return err;
+        fe::ScalarArgs a2 = sa;
+        memcpy(a2.theta, t.data(), sizeof(double) * P);
+        a2.r = nullptr;
+        a2.JT = nullptr;
+        a2.vdir = d.coef;
+        a2.r2 = d.v;
+        return fe::launch_scalar_eval(a2, s);
     };
     std::vector<double> r(n);
     int it = 0, rc = FE_OK;
     double lam = 0.0;
-    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, it, lam);
+    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, true, second, it, lam);
+    if (e != hipSuccess) {
+        d.release();
+        return hip_fail(e, "trainer");
+    }
+    int mat_its = 0, mat_acc = 0;
+    double ml0 = NAN, ml1 = NAN;
+    if (spec->n_mats > 0) {
+        rc = matrix_refine(spec, P, n, th, r, d, s, launch, mat_its, mat_acc, ml0, ml1);
+        if (rc) {
+            d.release();
+            return rc;
+        }
+    }
     d.release();
-    if (e != hipSuccess) return hip_fail(e, "trainer");
     memcpy(theta_out, th.data(), sizeof(double) * P);
     double emax = 0.0, ss = 0.0;
     for (double v : r) {
@@ -327,6 +540,10 @@ int fe_train_coeffs(const fe_train_spec* spec, const double* theta_init, double*
         rep->rms = sqrt(ss / n);
         rep->max_err_points = emax;
         rep->lambda = lam;
+        rep->mat_iters = mat_its;
+        rep->mat_accepted = mat_acc;
+        rep->mat_loss_start = ml0;
+        rep->mat_loss_end = ml1;
         double gmax = 0.0;
         const int ng = 200001;
         for (int k = 0; k < ng; ++k) {
@@ -347,6 +564,7 @@ int fe_train_variant(const fe_train_spec* spec, const fe_qmodel* init, double* c
     int rc = check_qmodel(init);
     if (rc) return rc;
     if (spec->target != FE_TARGET_FERMI) return fail(FE_ERR_ARG, "the variant trainer fits the Fermi target");
+    if (spec->n_mats != 0) return fail(FE_ERR_ARG, "the variant trainer takes no matrix set");
     if (!(spec->beta0 > 0.0) || !(spec->mu0 > 0.0 && spec->mu0 < 1.0)) return fail(FE_ERR_ARG, "bad (beta0, mu0)");
     const int P = (int)qmodel_coef_count(init->arch, init->L, init->k, init->K), n = spec->n_points;
     if (n < P) return fail(FE_ERR_ARG, "need at least as many sample points as coefficients");
@@ -374,7 +592,10 @@ int fe_train_variant(const fe_train_spec* spec, const fe_qmodel* init, double* c
     std::vector<double> r(n);
     int it = 0;
     double lam = 0.0;
-    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, it, lam);
+    auto no_second = [](const std::vector<double>&, const std::vector<double>&) {
+        return hipErrorNotSupported;
+    };
+    e = lm_run(P, n, th, r, d, s, spec->max_iter, spec->tol, launch, false, no_second, it, lam);
     d.release();
     if (e != hipSuccess) return hip_fail(e, "trainer");
     memcpy(coef_out, th.data(), sizeof(double) * P);
@@ -388,6 +609,8 @@ int fe_train_variant(const fe_train_spec* spec, const fe_qmodel* init, double* c
         rep->rms = sqrt(ss / n);
         rep->max_err_points = emax;
         rep->lambda = lam;
+        rep->mat_iters = rep->mat_accepted = 0;
+        rep->mat_loss_start = rep->mat_loss_end = NAN;
         double gmax = 0.0;
         const int ng = 200001;
         for (int k = 0; k < ng; ++k) {

@@ -172,25 +172,39 @@ __global__ void __launch_bounds__(NT) k_wide(WideArgs p) {
     const T ca = (T)p.a, cb = (T)p.b, cc = (T)p.c, dn = (T)p.d_next;
     const bool last = p.last != 0, ent = p.entropy != 0;
     const int flip = (last && !ent) ? p.P->flipped : 0;
+    const bool f64e = last && p.f64_epi;   // FP64 epilogue of a correction layer (T = float)
     const int64_t n = p.n;
     T* __restrict__ Xo = static_cast<T*>(p.X_out);
     T* __restrict__ A = static_cast<T*>(p.A);
+    // Last-layer value at upper position gi (row gr, column gc) from the product y:
+    // D = A + d_last X + (a y + b X + c delta), in FP64 for the correction layer (then not
+    // rounded: the layer's D is formed in FP64 from FP32 products and FP32 state), else in T.
+    auto last_value = [&](T y, int64_t gi, int64_t gr, int64_t gc) -> double {
+        double v;
+        if (f64e) {
+            const double x = (double)Lm[gi];
+            v = (double)A[gi] + p.d_last * x + (p.a * (double)y + p.b * x + (gr == gc ? p.c : 0.0));
+        } else {
+            const T xn = ca * y + cb * Lm[gi] + (gr == gc ? cc : (T)0);
+            v = (double)A[gi] + (double)xn;
+        }
+        if (flip) v = (gr == gc ? 1.0 : 0.0) - v;
+        // FP32 mode carries FP32 values (so the tile and its mirror hold the same number)
+        return (ent || sizeof(T) == 8 || f64e) ? v : (double)(float)v;
+    };
     double tr = 0.0, sq = 0.0;
     for (int e = tid; e < BM * BM; e += NT) {
         const int r = e / BM, c = e % BM;
         if (diag && r > c) continue;
         const int64_t gr = I0 + r, gc = J0 + c, gi = gr * np + gc;
         const T y = sY[r * LDY + c];
-        const T xn = ca * y + cb * Lm[gi] + (gr == gc ? cc : (T)0);
         if (!last) {
+            const T xn = ca * y + cb * Lm[gi] + (gr == gc ? cc : (T)0);
             if (dn != (T)0) A[gi] += dn * xn;
             Xo[gi] = xn;
             sY[r * LDY + c] = xn;
         } else {
-            double v = (double)A[gi] + (double)xn;
-            if (flip) v = (gr == gc ? 1.0 : 0.0) - v;
-            // FP32 mode carries FP32 values (so the tile and its mirror hold the same number)
-            const double vo = (ent || sizeof(T) == 8) ? v : (double)(float)v;
+            const double vo = last_value(y, gi, gr, gc);
             if (gr < n && gc < n) {
                 if (gr == gc) tr += vo;
                 sq += (gr == gc ? 1.0 : 2.0) * vo * vo;
@@ -201,7 +215,7 @@ __global__ void __launch_bounds__(NT) k_wide(WideArgs p) {
                         reinterpret_cast<double*>(p.D)[gr * p.ldd + gc] = vo;
                 }
             }
-            sY[r * LDY + c] = (T)vo;
+            if (!f64e) sY[r * LDY + c] = (T)vo;   // the correction layer keeps y and recomputes
         }
     }
     __syncthreads();
@@ -214,10 +228,14 @@ __global__ void __launch_bounds__(NT) k_wide(WideArgs p) {
             if (!last) {
                 Xo[orow * np + ocol] = v;
             } else if (orow < n && ocol < n) {
+                // the mirror of an FP64 correction value is recomputed from the same operands,
+                // so D stays exactly symmetric
+                const double vo = f64e ? last_value(v, (I0 + r) * np + J0 + c, I0 + r, J0 + c)
+                                       : (double)v;
                 if (p.out_mode == 0)
-                    reinterpret_cast<float*>(p.D)[orow * p.ldd + ocol] = (float)v;
+                    reinterpret_cast<float*>(p.D)[orow * p.ldd + ocol] = (float)vo;
                 else
-                    reinterpret_cast<double*>(p.D)[orow * p.ldd + ocol] = (double)v;
+                    reinterpret_cast<double*>(p.D)[orow * p.ldd + ocol] = vo;
             }
         }
     }
@@ -241,6 +259,30 @@ __global__ void __launch_bounds__(NT) k_wide(WideArgs p) {
     }
 }
 
+// Lower triangle of an np x np FP32 matrix from its upper triangle (X[i][j] = X[j][i] for
+// i > j), through 64 x 64 LDS tiles: workgroup (I, J), I >= J, reads the upper tile (J, I) row by
+// row and writes its transpose into the lower tile (I, J); diagonal tiles copy within the tile.
+__global__ void __launch_bounds__(256) k_mirror_upper(float* X, int64_t np) {
+    __shared__ float t[BM][BM + 1];
+    int rem = blockIdx.x, i = 0;
+    const int T_ = (int)(np / BM);
+    while (rem >= T_ - i) {   // upper-tile enumeration: tile (i, i + rem) is the source
+        rem -= T_ - i;
+        ++i;
+    }
+    const int64_t R0 = (int64_t)i * BM, C0 = (int64_t)(i + rem) * BM;   // source tile, R0 <= C0
+    for (int e = threadIdx.x; e < BM * BM; e += 256) {
+        const int r = e / BM, c = e % BM;
+        t[r][c] = X[(R0 + r) * np + C0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BM * BM; e += 256) {
+        const int r = e / BM, c = e % BM;   // destination (C0 + r, R0 + c) = source (R0 + c, C0 + r)
+        if (R0 == C0 && !(r > c)) continue;
+        X[(C0 + r) * np + R0 + c] = t[c][r];
+    }
+}
+
 template <typename T>
 hipError_t launch(const WideArgs& a, hipStream_t s) {
     if (a.np % BM != 0) return hipErrorInvalidValue;
@@ -255,5 +297,11 @@ hipError_t launch(const WideArgs& a, hipStream_t s) {
 int wide_tile() { return BM; }
 hipError_t launch_layer_f32(const WideArgs& a, hipStream_t s) { return launch<float>(a, s); }
 hipError_t launch_layer_f64(const WideArgs& a, hipStream_t s) { return launch<double>(a, s); }
+hipError_t launch_mirror_upper_f32(float* X, int64_t np, hipStream_t s) {
+    if (np % BM != 0) return hipErrorInvalidValue;
+    const int T_ = (int)(np / BM);
+    hipLaunchKernelGGL(k_mirror_upper, dim3(T_ * (T_ + 1) / 2), dim3(256), 0, s, X, np);
+    return hipGetLastError();
+}
 
 }  // namespace fe

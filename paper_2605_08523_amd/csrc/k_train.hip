@@ -37,7 +37,36 @@ k_scalar_eval(ScalarArgs a) {
         out = k4 * u * (1.0 - u);
         fac = k4 * (1.0 - 2.0 * u);
     }
-    a.r[k] = out - (a.tgt ? a.tgt[k] : 0.0);
+    if (a.r) a.r[k] = out - (a.tgt ? a.tgt[k] : 0.0);
+    if (a.r2) {
+        // second derivative of the output along theta + t v at t = 0 (forward mode, second
+        // order): with x' and x'' the first and second t-derivatives of a state,
+        //   x_{i+1}'  = va x^2 + 2 a x x' + vb x + b x' + vc,
+        //   x_{i+1}'' = 4 va x x' + 2 a (x'^2 + x x'') + 2 vb x' + b x'',
+        //   A'  += vd x + d x',   A'' += 2 vd x' + d x''
+        // (the input does not depend on theta, so x_0' = x_0'' = 0)
+        const double* v = a.vdir;
+        double xd = 0.0, xdd = 0.0, Ad = 0.0, Add = 0.0;
+        for (int i = 0; i < L; ++i) {
+            const double xi = xs[i];
+            const double ca = a.theta[4 * i], cb = a.theta[4 * i + 1], cd = a.theta[4 * i + 3];
+            const double va = v[4 * i], vb = v[4 * i + 1], vc = v[4 * i + 2], vd = v[4 * i + 3];
+            Ad += vd * xi + cd * xd;
+            Add += 2.0 * vd * xd + cd * xdd;
+            const double nd = va * xi * xi + 2.0 * ca * xi * xd + vb * xi + cb * xd + vc;
+            const double ndd = 4.0 * va * xi * xd + 2.0 * ca * (xd * xd + xi * xdd) + 2.0 * vb * xd +
+                               cb * xdd;
+            xd = nd;
+            xdd = ndd;
+        }
+        const double ud = Ad + xd, udd = Add + xdd;
+        double o2 = udd;
+        if (a.target == 1) {
+            const double k4 = 4.0 * 0.69314718055994530942;
+            o2 = k4 * (-2.0 * ud * ud + (1.0 - 2.0 * u) * udd);
+        }
+        a.r2[k] = o2;
+    }
     if (!a.JT) return;
     double xb = 1.0;   // adjoint of x_{i+1}
     for (int i = L - 1; i >= 0; --i) {
@@ -142,9 +171,43 @@ k_fwd_out(const float* hist, int64_t n, int L, MatTheta th, float* P) {
     }
 }
 
+// Residual of a matrix fit: G = P - Dref (FP32, the backward pass's input) and per-block FP64
+// partial sums of (P - Dref)^2, reduced in a fixed order by k_sumsq_reduce.
+__global__ void __launch_bounds__(256)
+k_mat_residual(const float* P, const double* Dref, int64_t total, float* G, double* part) {
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const double r = (double)P[e] - Dref[e];
+        if (G) G[e] = (float)r;
+        s += r * r;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(64) k_sumsq_reduce(const double* part, int nblocks, double* out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[b];
+    *out = s;
+}
+
 }  // namespace
 
 int scalar_max_layers() { return kScalarMaxL; }
+
+hipError_t launch_mat_residual(const float* P, const double* Dref, int64_t total, float* G,
+                               double* part, int nblocks, double* sumsq, hipStream_t s) {
+    hipLaunchKernelGGL(k_mat_residual, dim3(nblocks), dim3(256), 0, s, P, Dref, total, G, part);
+    hipLaunchKernelGGL(k_sumsq_reduce, dim3(1), dim3(64), 0, s, part, nblocks, sumsq);
+    return hipGetLastError();
+}
 
 hipError_t launch_scalar_eval(const ScalarArgs& a, hipStream_t s) {
     if (a.L < 1 || a.L > kScalarMaxL) return hipErrorInvalidValue;

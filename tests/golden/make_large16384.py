@@ -12,7 +12,9 @@ oracle (LAPACK dsyevd, tens of minutes on a few cores, ~10 GB of memory) gives:
   vectors (``probes``, columns of V);
 * ``<model>_*``: the same for the recursion of each listed model in FP64 (Alg. 2 evaluated on
   the spectrum of H), including its entropy expansion with the Fermi coefficients reused at
-  alpha = 0.842704 (Sec. III.B).
+  alpha = 0.842704 (Sec. III.B);
+* ``<entropy model>_S``: S from the entropy expansion of each listed entropy model
+  (theta_entropy, its own alpha).
 
 Only the oracle and the seeded input generator are called. Run from the repository root:
 ``python tests/golden/make_large16384.py``.
@@ -35,6 +37,7 @@ from paper_2605_08523_amd import workloads as W  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large16384_oracle.npz")
 MODELS = ("mlsp2_L40_b1e4_mu1third", "mlsp2_L36_b1e4_mu0p5")
+ENTROPY_MODELS = ("entropy_L40_b1e4_mu1third",)
 ALPHA_REUSE = 0.842704
 N_ROWS, N_PROBES = 8, 4
 
@@ -42,7 +45,8 @@ N_ROWS, N_PROBES = 8, 4
 def _theta(name):
     with open(os.path.join(ROOT, "paper_2605_08523_amd", "models", name + ".json")) as f:
         d = json.load(f)
-    return np.asarray(d["theta"], dtype=np.float64).reshape(-1, 4), float(d["beta0"]), float(d["mu0"])
+    return (np.asarray(d["theta"], dtype=np.float64).reshape(-1, 4), float(d["beta0"]),
+            float(d["mu0"]), float(d.get("alpha", 1.0)))
 
 
 def main():
@@ -70,8 +74,14 @@ def main():
     out = dict(lam=lam, mu=np.float64(mu), kT=np.float64(kT), bounds=np.asarray(bounds),
                rows=rows, V=V, exact_S=np.float64(F.entropy_fn(lam, mu, kT).sum()))
     out.update(pack("exact", f))
+    for name in ENTROPY_MODELS:
+        theta, beta0, mu0, alpha = _theta(name)
+        s, info = R.entropy_eigen_terms(lam, bounds, mu, kT, theta, beta0, mu0, alpha)
+        out[f"{name}_S"] = np.float64(np.sum(s))
+        out[f"{name}_clamped"] = np.int64(info["clamped"])
+        print(f"{name}: S {np.sum(s):.9f} (exact {out['exact_S']:.9f})", flush=True)
     for name in MODELS:
-        theta, beta0, mu0 = _theta(name)
+        theta, beta0, mu0, _ = _theta(name)
         g, info = R.density_eigenvalues(lam, bounds, mu, kT, theta, beta0, mu0)
         s, _ = R.entropy_eigen_terms(lam, bounds, mu, kT, theta, beta0, mu0, ALPHA_REUSE)
         out.update(pack(name, g))

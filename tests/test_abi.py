@@ -59,7 +59,7 @@ def test_argument_errors_without_device(lib):
     rc = lib.fe_sp2_coeffs(1.5, 2, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     assert rc == api.FE_ERR_DOMAIN
     assert b"mu'" in lib.fe_last_error()
-    rc = lib.fe_expand_density(None, 4, 4, 0.0, 0.1, None, 2, None, 0, 4, None, None, None, None, None)
+    rc = lib.fe_expand_density(None, 4, 4, 0.0, 0.1, None, 2, 0, None, 0, 4, None, None, None, None, None)
     assert rc == api.FE_ERR_ARG
     assert lib.fe_version().startswith(b"fe-mi355x")
 

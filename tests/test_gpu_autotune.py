@@ -43,7 +43,7 @@ def test_autotune_table_and_parity(api, paper_model):
     Drec, _ = R.mlsp2_density(H, 0.1, 0.1, m.theta, m.beta0, m.mu0)
     fro = np.linalg.norm(D.double().cpu().numpy() - Drec) / 1500
     print(f"[autotune] n=1500 under {api.autotune_lookup(1500, ws=ws)}: |dD|_F/N={fro:.3e}", flush=True)
-    assert fro <= 1e-5
+    assert fro <= 10 * 9.848e-08          # measured on MI355X (the schedules agree to ~10%)
     api.autotune_clear()
     assert api.autotune_lookup(4096, ws=ws) == default_4096
     torch.cuda.synchronize()
@@ -88,7 +88,7 @@ def test_autotune_on_input(api, paper_model, monkeypatch):
     Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
     fro = np.linalg.norm(D - Drec) / n
     print(f"[autotune_input] |dD|_F/N={fro:.3e}", flush=True)
-    assert fro <= 1e-5
+    assert fro <= 10 * 4.516e-08          # measured on MI355X
     # argument checks as for the expansion: no timing runs, no table entry
     api.autotune_clear()
     with pytest.raises(api.FeError):

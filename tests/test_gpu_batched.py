@@ -6,6 +6,7 @@ import pytest
 from oracle import fermi as F
 from oracle import recursion as R
 from paper_2605_08523_amd import workloads as W
+from parity import within
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,6 +34,11 @@ def uneven_batch(count, seed0, n_lo=64, n_hi=400):
     return mats
 
 
+# measured on MI355X: ||dD||_F/N of each item against the oracle recursion
+MEASURED_BATCH12 = [1.215e-07, 1.160e-07, 2.853e-07, 2.305e-07, 1.273e-07, 6.448e-08, 1.481e-07,
+                    1.708e-07, 2.440e-07, 1.146e-07, 1.676e-07, 1.236e-07]
+
+
 def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch):
     m = paper_model
     mats = uneven_batch(12, 500)
@@ -53,9 +59,10 @@ def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch):
         assert float(plan.S[b]) == float(S1)
         Drec, _ = R.mlsp2_density(it["Hn"], it["mu"], it["kT"], m.theta, m.beta0, m.mu0)
         n = Drec.shape[0]
-        fro = np.linalg.norm(Db.double().cpu().numpy() - Drec) / n
-        print(f"[batch item {b}] N={n} |dD|_F/N={fro:.3e}", flush=True)
-        assert fro <= 1e-5
+        E = Db.double().cpu().numpy() - Drec
+        fro = np.linalg.norm(E) / n
+        print(f"[batch item {b}] N={n} |dD|_F/N={fro:.3e} max|dD|={np.max(np.abs(E)):.3e}", flush=True)
+        within(f"batch item {b}", fro, MEASURED_BATCH12[b], cap=1e-5)
 
 
 def test_batch_status_errors_and_replay(api, paper_model):
@@ -85,6 +92,11 @@ def test_batch_status_errors_and_replay(api, paper_model):
     torch.cuda.synchronize()
 
 
+MEASURED_FAMILY = [4.620e-08, 1.230e-07, 1.210e-07, 1.313e-07, 3.856e-08, 1.133e-07, 1.922e-07,
+                   1.063e-07, 7.816e-08, 3.995e-08, 9.787e-08, 7.314e-08, 3.996e-08, 6.996e-08,
+                   1.483e-07, 5.047e-08]
+
+
 def test_batch_config_family(api):
     """Items of the uneven-batch workload family (N in [64, 768], kT in [0.01, 0.3], mu inside
     the spectrum), with a clamp warning where beta' exceeds the paper model's region."""
@@ -100,9 +112,11 @@ def test_batch_config_family(api):
         Drec, info = R.mlsp2_density(it["Hn"], it["mu"], it["kT"], m.theta, m.beta0, m.mu0)
         assert st[b] == (api.FE_WARN_BETA_CLAMPED if info["clamped"] else 0)
         n = Drec.shape[0]
-        fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - Drec) / n
-        print(f"[batch family {b}] N={n} clamped={info['clamped']} |dD|_F/N={fro:.3e}", flush=True)
-        assert fro <= 1e-5
+        E = plan.D[b].double().cpu().numpy() - Drec
+        fro = np.linalg.norm(E) / n
+        print(f"[batch family {b}] N={n} clamped={info['clamped']} |dD|_F/N={fro:.3e} "
+              f"max|dD|={np.max(np.abs(E)):.3e}", flush=True)
+        within(f"batch family {b}", fro, MEASURED_FAMILY[b], cap=1e-5)
 
 
 BANK = ["mlsp2_L20_b300_mu1third", "mlsp2_L22_b600_mu1third", "mlsp2_L26_b1500_mu1third",
@@ -122,6 +136,15 @@ def expected_choice(H, mu, kT, bank):
     fits = [k for k, m in enumerate(bank)
             if beta_p <= min(m.mu0 / mu_p, (1 - m.mu0) / (1 - mu_p)) * m.beta0]
     return min(fits, key=lambda k: (bank[k].L, -bank[k].beta0))
+
+
+# measured on MI355X: ||dD||_F/N of each item (with its selected model) against the exact D
+MEASURED_BANK = {
+    "mu1third": [2.177e-07, 1.304e-07, 7.419e-08, 2.869e-07, 4.626e-07, 1.035e-07, 1.755e-07,
+                 8.431e-08, 4.235e-07, 1.860e-07],
+    "mixed": [2.177e-07, 1.304e-07, 1.548e-07, 7.773e-07, 5.245e-07, 1.035e-07, 1.111e-07,
+              2.012e-07, 1.241e-06, 3.623e-07],
+}
 
 
 @pytest.mark.parametrize("bank_name", ["mu1third", "mixed"])
@@ -160,9 +183,16 @@ def test_model_bank_batch(api, monkeypatch, bank_name):
         assert float(plan.S[b]) == float(S1)
         ref = F.density(it["Hn"], it["mu"], it["kT"])
         n = it["Hn"].shape[0]
-        fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - ref["D"]) / n
-        print(f"[bank item {b}] N={n} kT={it['kT']} model {m.name} |dD|_F/N={fro:.3e}", flush=True)
-        assert fro <= 1e-5
+        E = plan.D[b].double().cpu().numpy() - ref["D"]
+        fro = np.linalg.norm(E) / n
+        print(f"[bank item {b}] N={n} kT={it['kT']} model {m.name} |dD|_F/N={fro:.3e} "
+              f"max|dD|={np.max(np.abs(E)):.3e}", flush=True)
+        within(f"bank {bank_name} item {b}", fro, MEASURED_BANK[bank_name][b], cap=1e-5)
+
+
+MEASURED_TILE64 = [1.844e-07, 2.978e-07, 3.710e-07, 1.843e-07, 3.450e-07, 2.791e-07, 9.276e-08,
+                   2.049e-07, 1.962e-07, 1.840e-07, 2.025e-07, 1.895e-07, 1.675e-07, 2.516e-07,
+                   2.942e-07, 1.126e-07]
 
 
 def test_batch_tile_64_and_autotune(api, paper_model):
@@ -193,7 +223,8 @@ def test_batch_tile_64_and_autotune(api, paper_model):
         fro = np.linalg.norm(plan.D[b].double().cpu().numpy() - Drec) / n
         d = float((plan.D[b] - D128[b]).abs().max())
         print(f"[tile64 item {b}] N={n} |dD|_F/N={fro:.3e} max|D64 - D128|={d:.2e}", flush=True)
-        assert fro <= 1e-5 and d < 1e-4
+        within(f"tile64 item {b}", fro, MEASURED_TILE64[b], cap=1e-5)
+        assert d == 0.0, "both tile sizes sum each element over K in the same order"
         assert torch.equal(plan.D[b], plan.D[b].T)
     assert torch.allclose(plan.S, S128, rtol=1e-5, atol=1e-6)
     tile, ms = plan.autotune()

@@ -3,9 +3,11 @@
 Tolerances:
   * FP64 mode vs the oracle recursion with the same coefficients: max |dD| <= 1e-11
     (rounding of ~L dense FP64 products with entries O(1)).
-  * 16-bit split modes: ||dD||_F / N <= 1e-5 against both the oracle recursion and the exact
-    density matrix (the accuracy bar of the expansion); D must be exactly symmetric.
-  * Every result prints ||dD||_F/N, max |dD| and |dTr D| against the exact definition.
+  * 16-bit split modes: ||dD||_F / N within the bar (1e-5) and within 10x the error measured on
+    MI355X for the same case, against the oracle recursion and the exact density matrix; max |dD|
+    and |dTr D| within 10x their measured values; the FP64 traces against the oracle's Tr D and
+    sum D_ij^2 within what the element-wise error allows (tests/parity.py); D exactly symmetric.
+  * Every result prints ||dD||_F/N, max |dD| and |dTr D|.
 """
 import numpy as np
 import pytest
@@ -13,6 +15,7 @@ import pytest
 from oracle import fermi as F
 from oracle import recursion as R
 from paper_2605_08523_amd import workloads as W
+from parity import BAR, check_errors, traces_consistent, within
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +79,24 @@ CASES = [
 ]
 
 
+# measured on MI355X with the paper's 26-layer model: (||dD||_F/N, max |dD|, |dTr D|) against
+# the exact D (the recursion's are the same to three digits)
+MEASURED_SPLIT = {
+    ("dense128", "fp16x2"): (3.083e-07, 6.791e-06, 1.375e-04),
+    ("dense128", "bf16x2"): (9.121e-06, 1.999e-04, 2.051e-03),
+    ("dense200_noflip", "fp16x2"): (2.126e-07, 6.750e-06, 1.289e-04),
+    ("dense200_noflip", "bf16x2"): (6.127e-06, 1.940e-04, 1.191e-03),
+    ("dense384", "fp16x2"): (1.341e-07, 5.636e-06, 1.985e-04),
+    ("dense384", "bf16x2"): (3.025e-06, 1.416e-04, 1.307e-03),
+    ("anderson512", "fp16x2"): (1.366e-07, 2.928e-06, 3.690e-04),
+    ("anderson512", "bf16x2"): (1.371e-06, 5.108e-05, 2.804e-04),
+    ("dense1000", "fp16x2"): (1.599e-07, 2.019e-05, 8.429e-04),
+    ("dense1000", "bf16x2"): (3.109e-06, 2.628e-04, 1.117e-02),
+    ("banded700", "fp16x2"): (1.164e-07, 1.108e-05, 5.288e-04),
+    ("banded700", "bf16x2"): (2.554e-06, 2.504e-04, 2.190e-03),
+}
+
+
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_split_modes_against_oracle(api, paper_model, prec, name, make):
@@ -85,10 +106,13 @@ def test_split_modes_against_oracle(api, paper_model, prec, name, make):
     D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec)
     Drec, oinfo = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
     exact = F.density(H, mu, kT)
-    fro_r, _ = report(f"{name} {prec} vs recursion", D, Drec)
-    fro_e, _ = report(f"{name} {prec} vs exact", D, exact["D"], tr, exact["trD"])
+    fro_r, mx_r = report(f"{name} {prec} vs recursion", D, Drec)
+    fro_e, mx_e = report(f"{name} {prec} vs exact", D, exact["D"], tr, exact["trD"])
     assert torch.equal(Dt, Dt.T), "D must be exactly symmetric"
-    assert fro_r <= 1e-5 and fro_e <= 1e-5
+    meas = MEASURED_SPLIT[(name, prec)]
+    check_errors(f"{name} {prec} vs recursion", fro_r, mx_r, meas)
+    check_errors(f"{name} {prec} vs exact", fro_e, mx_e, meas, abs(tr - exact["trD"]))
+    traces_consistent(f"{name} {prec}", D, exact["D"], tr, tr2, exact["trD"], exact["trD2"])
     assert info["flipped"] == int(oinfo["flipped"])
     # the kernel's FP64 traces agree with the trace of the matrix it wrote
     assert tr == pytest.approx(np.trace(D), abs=1e-9 * H.shape[0])
@@ -104,8 +128,10 @@ def test_anderson_4096_fp16x2(api, paper_model):
     D, tr, tr2, info, Dt = run(api, c["H"], c["mu"], c["kT"], m, "fp16x2")
     assert info["rc"] == 0 and info["beta_p"] == pytest.approx(280.0, rel=0.01)
     exact = F.density(c["H"], c["mu"], c["kT"])
-    fro, _ = report("anderson4096 fp16x2 vs exact", D, exact["D"], tr, exact["trD"])
-    assert fro <= 1e-5
+    fro, mx = report("anderson4096 fp16x2 vs exact", D, exact["D"], tr, exact["trD"])
+    check_errors("anderson4096 fp16x2 L26", fro, mx, (4.391e-08, 4.770e-06, 2.260e-03),
+                 abs(tr - exact["trD"]))
+    traces_consistent("anderson4096 fp16x2 L26", D, exact["D"], tr, tr2, exact["trD"], exact["trD2"])
     assert torch.equal(Dt, Dt.T)
     # the benchmark's step: the model the bank selects for this lattice, both 16-bit splits
     import bench
@@ -114,13 +140,59 @@ def test_anderson_4096_fp16x2(api, paper_model):
     Hd = torch.from_numpy(c["H"]).cuda()
     k = api.select_model(Hd, c["mu"], c["kT"], bank)
     assert bench.BANK[k] == "mlsp2_L20_b300_mu0p5"
+    measured = {"fp16x2": (2.400e-08, 2.864e-06, 1.042e-03), "bf16x2": (3.531e-07, 4.468e-05, 2.175e-03)}
     for prec in ("fp16x2", "bf16x2"):
         print(f"case anderson4096 {prec} bank model {bench.BANK[k]}", flush=True)
         D, tr, tr2, info, Dt = run(api, c["H"], c["mu"], c["kT"], bank[k], prec)
         assert info["rc"] == 0
-        fro, _ = report(f"anderson4096 {prec} bank vs exact", D, exact["D"], tr, exact["trD"])
-        assert fro <= 1e-5
+        fro, mx = report(f"anderson4096 {prec} bank vs exact", D, exact["D"], tr, exact["trD"])
+        check_errors(f"anderson4096 {prec} bank", fro, mx, measured[prec], abs(tr - exact["trD"]))
+        traces_consistent(f"anderson4096 {prec} bank", D, exact["D"], tr, tr2, exact["trD"],
+                          exact["trD2"])
         assert torch.equal(Dt, Dt.T)
+        # the same with the final correction layer (FP32 product, FP64 epilogue, float64 D)
+        print(f"case anderson4096 {prec} bank model final correction", flush=True)
+        Dc, trc, tr2c, info, Dct = run(api, c["H"], c["mu"], c["kT"], bank[k], prec,
+                                       out_dtype=torch.float64, final_correction=True)
+        assert info["rc"] == 0
+        froc, mxc = report(f"anderson4096 {prec} bank final-correction vs exact", Dc, exact["D"],
+                           trc, exact["trD"])
+        check_errors(f"anderson4096 {prec} bank final correction", froc, mxc,
+                     {"fp16x2": (2.832e-08, 4.838e-06, 3.253e-03),
+                      "bf16x2": (3.518e-07, 4.638e-05, 1.337e-03)}[prec], abs(trc - exact["trD"]))
+        assert torch.equal(Dct, Dct.T)
+        assert not torch.equal(Dct, Dct.float().double()), "an FP64 D, not FP32 values"
+        assert trc == pytest.approx(np.trace(Dc), abs=1e-9 * 4096)
+        assert tr2c == pytest.approx(np.sum(Dc * Dc), abs=1e-9 * 4096)
+
+
+@pytest.mark.parametrize("sch", ["dp", "sk", "sk2"])
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
+def test_final_correction_against_oracle(api, sk_ws, paper_model, monkeypatch, sch, prec):
+    """The final correction layer (last product by FP32 MFMA from the FP32 state, FP64 epilogue,
+    float64 D) against the oracle's recursion with the same model, every schedule (the
+    correction's 64 x 64 tiles follow split layers of 128 and 256 tiles), on a ragged size."""
+    monkeypatch.setenv("FE_SCHEDULE", sch)
+    m = paper_model
+    H = W.random_dense(1100, 26)
+    mu, kT = 0.05, 0.1
+    Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
+    print(f"case final correction {prec} {sch}", flush=True)
+    D0, _, _, _, _ = run(api, H, mu, kT, m, prec, ws=sk_ws)
+    Dc, trc, tr2c, info, Dct = run(api, H, mu, kT, m, prec, ws=sk_ws, out_dtype=torch.float64,
+                                   final_correction=True)
+    fro0, mx0 = report(f"final correction {prec} {sch}: without", D0, Drec)
+    froc, mxc = report(f"final correction {prec} {sch}: with", Dc, Drec, trc, float(np.trace(Drec)))
+    assert info["rc"] == 0
+    assert torch.equal(Dct, Dct.T)
+    # measured on MI355X: the correction layer leaves the error where it was (1.51e-7 / 1.12e-7 /
+    # 1.13e-7 FP16x2, 2.83e-6 / 2.83e-6 / 2.84e-6 BF16x2 for dp / sk2 / sk): the error comes from the
+    # earlier layers, amplified by the later layers' slope, not from the last product
+    check_errors(f"final correction {prec} {sch}", froc, mxc,
+                 {"fp16x2": (1.509e-07, 1.567e-05), "bf16x2": (2.843e-06, 2.604e-04)}[prec])
+    within(f"final correction {prec} {sch} vs without", froc, fro0, factor=1.1)
+    assert trc == pytest.approx(np.trace(Dc), abs=1e-9 * 1100)
+    assert tr2c == pytest.approx(np.sum(Dc * Dc), abs=1e-9 * 1100)
 
 
 def test_strided_inputs_and_fp64_output(api, paper_model):
@@ -135,8 +207,8 @@ def test_strided_inputs_and_fp64_output(api, paper_model):
     torch.cuda.synchronize()
     Dn = out.cpu().numpy()
     Drec, _ = R.mlsp2_density(H, 0.1, 0.1, m.theta, m.beta0, m.mu0)
-    fro, _ = report("strided fp64-out", Dn, Drec)
-    assert fro <= 1e-5
+    fro, mx = report("strided fp64-out", Dn, Drec)
+    check_errors("strided fp64-out", fro, mx, (2.419e-07, 1.361e-05))
     assert torch.all(full[:, 300:] == 7.0)      # padding columns of the output untouched
 
 
@@ -150,8 +222,8 @@ def test_clamp_warning(api, paper_model):
     Drec, oinfo = R.mlsp2_density(H, 0.0, kT, m.theta, m.beta0, m.mu0)
     assert oinfo["clamped"]
     assert info["beta_p"] == pytest.approx(oinfo["beta_p"], rel=1e-12)
-    fro, _ = report("clamped", D, Drec)
-    assert fro <= 1e-5
+    fro, mx = report("clamped", D, Drec)
+    check_errors("clamped", fro, mx, (1.080e-07, 2.304e-06))
 
 
 def test_domain_and_nonfinite_errors(api, paper_model):
@@ -213,12 +285,41 @@ def test_entropy_against_oracle(api, paper_model, prec):
     Sex = F.entropy(H, mu, kT)
     print(f"[entropy {prec}] S={S:.10f} S_rec={Srec:.10f} S_exact={Sex:.10f} "
           f"rel(rec)={abs(S - Srec) / Srec:.3e} rel(exact)={abs(S - Sex) / Sex:.3e}", flush=True)
-    tol = 1e-10 if prec == "fp64" else 1e-4
-    assert abs(S - Srec) <= tol * abs(Srec)
+    if prec == "fp64":
+        assert abs(S - Srec) <= 1e-10 * abs(Srec)
+    else:
+        within("entropy fp16x2 relative", abs(S - Srec) / abs(Srec), 3.184e-06)
 
 
-# n = 5700 hybrid schedule against the oracle: bounds on ||dD||_F/N, max|dD| and |dTr D|
-HYBRID_BOUND = dict(fro=1e-5, max=1e-3, tr=1e-6 * 5700)
+# n = 5700 hybrid schedule against the oracle: 10x the measured ||dD||_F/N (2.48e-8), max |dD|
+# (7.92e-6) and |dTr D| (1.96e-3), both schedules
+HYBRID_BOUND = dict(fro=2.5e-7, max=8e-5, tr=2e-2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+def test_theta_entropy_against_oracle(api, prec):
+    """S with the trained entropy coefficients (theta_entropy, Sec. III.B) of the paper model's
+    (1500, 1/3) setting, against the oracle's FP64 entropy recursion with the same coefficients and
+    against the exact entropy: theta_entropy is closer to the exact S than theta_fermi reused."""
+    from paper_2605_08523_amd import models
+    me = models.load("entropy_L26_b1500_mu1third")
+    mf = models.load("mlsp2_L26_b1500_mu1third")
+    H = W.random_dense(128 if prec == "fp64" else 500, 16)
+    mu, kT = 0.05, 0.1
+    Hd = torch.from_numpy(H).cuda()
+    S, _ = api.expand_entropy(Hd, mu, kT, me, me.alpha, prec=prec, want_info=True)
+    Sf, _ = api.expand_entropy(Hd, mu, kT, mf, 0.842704, prec=prec)
+    S, Sf = float(S), float(Sf)
+    Srec, _ = R.entropy_expansion(H, mu, kT, me.theta, me.beta0, me.mu0, me.alpha)
+    Sex = F.entropy(H, mu, kT)
+    print(f"[theta_entropy {prec}] S={S:.10f} S_rec={Srec:.10f} S_exact={Sex:.10f} "
+          f"rel(rec)={abs(S - Srec) / Srec:.3e} rel(exact)={abs(S - Sex) / Sex:.3e} "
+          f"theta_fermi rel(exact)={abs(Sf - Sex) / Sex:.3e}", flush=True)
+    if prec == "fp64":
+        assert abs(S - Srec) <= 1e-10 * abs(Srec)
+        assert abs(S - Sex) < abs(Sf - Sex)
+    else:
+        within("theta_entropy fp16x2 relative", abs(S - Srec) / abs(Srec), 9.602e-07)
 
 
 @pytest.fixture(scope="module")
@@ -228,6 +329,20 @@ def sk_ws(api):
     yield ws
     torch.cuda.synchronize()
     ws.close()
+
+
+# measured on MI355X: (||dD||_F/N, max |dD|) against the oracle recursion
+MEASURED_SCHEDULES = {
+    ("dense300", "fp16x2", "dp"): (2.184e-07, 7.985e-06), ("dense300", "fp16x2", "sk"): (1.980e-07, 7.143e-06),
+    ("dense300", "fp16x2", "sk2"): (1.918e-07, 7.348e-06), ("dense300", "bf16x2", "dp"): (6.060e-06, 2.509e-04),
+    ("dense300", "bf16x2", "sk"): (6.126e-06, 2.499e-04), ("dense300", "bf16x2", "sk2"): (6.037e-06, 2.507e-04),
+    ("dense1000", "fp16x2", "dp"): (1.496e-07, 1.335e-05), ("dense1000", "fp16x2", "sk"): (1.134e-07, 9.072e-06),
+    ("dense1000", "fp16x2", "sk2"): (1.159e-07, 9.384e-06), ("dense1000", "bf16x2", "dp"): (2.920e-06, 2.616e-04),
+    ("dense1000", "bf16x2", "sk"): (2.925e-06, 2.569e-04), ("dense1000", "bf16x2", "sk2"): (2.909e-06, 2.618e-04),
+    ("banded1700", "fp16x2", "dp"): (4.708e-08, 5.837e-06), ("banded1700", "fp16x2", "sk"): (4.729e-08, 6.111e-06),
+    ("banded1700", "fp16x2", "sk2"): (4.694e-08, 5.837e-06), ("banded1700", "bf16x2", "dp"): (1.030e-06, 1.997e-04),
+    ("banded1700", "bf16x2", "sk"): (1.032e-06, 1.996e-04), ("banded1700", "bf16x2", "sk2"): (1.028e-06, 1.870e-04),
+}
 
 
 @pytest.mark.parametrize("schedule", ["dp", "sk", "sk2"])
@@ -243,10 +358,12 @@ def test_both_schedules(api, sk_ws, paper_model, monkeypatch, schedule, prec, na
     print(f"case {name} {prec} schedule={schedule}", flush=True)
     D, tr, tr2, info, Dt = run(api, H, mu, kT, m, prec, ws=sk_ws)
     Drec, _ = R.mlsp2_density(H, mu, kT, m.theta, m.beta0, m.mu0)
-    fro, _ = report(f"{name} {prec} {schedule} vs recursion", D, Drec)
+    fro, mx = report(f"{name} {prec} {schedule} vs recursion", D, Drec)
     assert torch.equal(Dt, Dt.T)
-    assert fro <= 1e-5
+    check_errors(f"{name} {prec} {schedule}", fro, mx, MEASURED_SCHEDULES[(name, prec, schedule)])
     assert tr == pytest.approx(np.trace(D), abs=1e-9 * n)
+    traces_consistent(f"{name} {prec} {schedule}", D, Drec, tr, tr2, float(np.trace(Drec)),
+                      float(np.sum(Drec * Drec)))
 
 
 def test_schedules_agree(api, sk_ws, paper_model, monkeypatch):
@@ -398,6 +515,14 @@ def test_sp2_projector_through_the_layer_kernel(api):
         assert abs(tr - nb) <= 1e-9 and abs(tr - tr2) <= 1e-9
 
 
+# measured on MI355X: (||dD||_F/N, max |dD|) against the oracle recursion
+MEASURED_FORMS = {
+    ("affine", "dp"): (3.412e-07, 3.535e-05), ("affine", "sk"): (2.509e-07, 2.102e-05),
+    ("affine", "sk2"): (2.555e-07, 2.542e-05), ("mlsp2", "dp"): (1.508e-07, 1.775e-05),
+    ("mlsp2", "sk"): (1.163e-07, 1.057e-05), ("mlsp2", "sk2"): (1.181e-07, 1.093e-05),
+}
+
+
 @pytest.mark.parametrize("sch", ["dp", "sk", "sk2"])
 def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
     """The squared-affine layer form (operand = shifted state, no FP32 state copy; FE_FORM=affine)
@@ -422,8 +547,8 @@ def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
         Hd = torch.from_numpy(H).cuda()
         S, _ = api.expand_entropy(Hd, mu, kT, m, 0.842704, prec=prec, ws=sk_ws)
         torch.cuda.synchronize()
-        fro, _ = report(f"{form} {sch} {prec} vs recursion", D, Drec)
-        assert fro <= 1e-5
+        fro, mx = report(f"{form} {sch} {prec} vs recursion", D, Drec)
+        check_errors(f"{form} {sch}", fro, mx, MEASURED_FORMS[(form, sch)])
         assert torch.equal(Dt, Dt.T)
         out[form] = (D, float(S), tr)
     d = np.max(np.abs(out["affine"][0] - out["mlsp2"][0]))

@@ -9,6 +9,7 @@ import pytest
 from oracle import fermi as F
 from paper_2605_08523_amd import models
 from paper_2605_08523_amd import workloads as W
+from parity import within
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -30,6 +31,11 @@ CASES = [
     ("banded700_30pc", lambda: W.banded_decay(700, 8.0, 2.0, 6), 0.2, 0.3, None, "bf16x2"),
     ("dense128_half_fp64", lambda: W.random_dense(128, 0), 0.1, 0.5, None, "fp64"),
 ]
+
+
+# measured on MI355X: ||dD||_F/N of the final iterate against the exact D at the oracle's mu
+MEASURED_FILLING = {"anderson512_half": 5.731e-08, "banded700_30pc": 2.788e-06,
+                    "dense128_half_fp64": 5.625e-10, "dense300_40pc_low_guess": 1.763e-07}
 
 
 @pytest.mark.parametrize("name,make,kT,filling,mu_init,prec", CASES)
@@ -57,7 +63,7 @@ def test_filling_against_oracle(api, paper_model, name, make, kT, filling, mu_in
     f = 1.0 / (1.0 + np.exp((ex_lam - mu_ref) / kT))
     dn_dmu = np.sum(f * (1 - f)) / kT
     assert abs(mu - mu_ref) <= 1e-5 * n / dn_dmu + 1e-9
-    assert fro <= 1e-5
+    within(f"filling {name} |dD|_F/N", fro, MEASURED_FILLING[name], cap=1e-5)
     assert torch.equal(D, D.T)
 
 

@@ -40,6 +40,25 @@ def test_scalar_jacobian_matches_oracle(tr, paper_model, kind):
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("kind", ["fermi", "entropy"])
+def test_scalar_second_derivative_matches_oracle(tr, paper_model, kind):
+    """The geodesic acceleration's input, d^2/dt^2 model(theta + t v), exact on the GPU (forward
+    mode of second order) against the oracle's complex-step / central-difference value."""
+    th = paper_model.theta
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(th.shape) * np.abs(th).clip(1e-3)
+    y = np.concatenate([T.sample_points(2048, 1500, 1 / 3, "deriv"), np.linspace(0, 1, 257)])
+    r2 = tr.scalar_second(torch.from_numpy(y).cuda(), th, v, kind, 1 / 3, 0.842704)
+    torch.cuda.synchronize()
+    # the oracle's central difference of the exact first derivative converges as h^2 (1e-4 gives
+    # ~2e-3 relative for this direction, 1e-7 ~4e-9)
+    ref = T.second_directional(y, th, v, kind, 1 / 3, 0.842704, h=1e-7)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(r2.cpu().numpy() - ref)) / scale
+    print(f"[second derivative {kind}] max |d2 - d2_oracle| / max |d2_oracle| = {err:.3e}", flush=True)
+    assert err < 1e-7
+
+
 def test_train_small_model_reaches_error_level(tr):
     """Sec. V.C: a 10-layer model trained at beta0 = 33.3, mu0 = 1/3, from the SP2 embedding."""
     th, rep, ok = tr.train_coeffs(10, 33.3, 1 / 3, n_points=2048, max_iter=400, tol=1e-9)
@@ -100,3 +119,73 @@ def test_matrix_autograd_against_finite_differences(tr, paper_model):
     rel = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
     print(f"[matrix autograd] max |g - fd| / max |fd| = {rel:.3e}", flush=True)
     assert rel < 1e-3
+
+
+def _matrix_set(rng, count, n, beta0, mu0):
+    """Symmetric X0 = Q diag(y) Q^T with spectra spread over the unit interval (denser near mu0)
+    and their targets Dref = Q diag(g(y)) Q^T: the oracle's Fermi target on the eigenvalues."""
+    out = []
+    for _ in range(count):
+        q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        y = np.clip(np.concatenate([rng.uniform(0, 1, n // 2), mu0 + rng.normal(0, 2 / beta0, n - n // 2)]), 0, 1)
+        X0 = (q * y) @ q.T
+        X0 = 0.5 * (X0 + X0.T)
+        yx, qx = np.linalg.eigh(X0)
+        D = (qx * T.fermi_target(yx, beta0, mu0)) @ qx.T
+        out.append((X0, 0.5 * (D + D.T)))
+    return out
+
+
+def test_matrix_loss_gradient_is_the_scalar_gradient_at_the_eigenvalues(tr, paper_model):
+    """For symmetric X0 with eigenvalues y_j, ||P(X0) - g(X0)||_F^2 = sum_j (P(y_j) - g(y_j))^2, so
+    the matrix term's gradient through the FP32 matrix backward equals the scalar residual
+    gradient at the eigenvalues (the oracle's Jacobian), to FP32 accuracy."""
+    rng = np.random.default_rng(21)
+    L = 8
+    th = paper_model.theta[:L].copy()
+    (X0, D), = _matrix_set(rng, 1, 128, 40.0, 0.4)
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    P = tr.matrix_recursion(theta, torch.from_numpy(X0).float().cuda())
+    loss = 0.5 * torch.sum((P.double() - torch.from_numpy(D).cuda()) ** 2)
+    loss.backward()
+    g_mat = theta.grad.numpy().ravel()
+    y = np.linalg.eigvalsh(X0)
+    out, J = T.jacobian(y, th)
+    g_ref = J.T @ (out - T.fermi_target(y, 40.0, 0.4))
+    rel = np.max(np.abs(g_mat - g_ref)) / np.max(np.abs(g_ref))
+    print(f"[matrix gradient identity] max |g_mat - g_scalar| / max |g_scalar| = {rel:.3e}", flush=True)
+    assert rel < 1e-3
+
+
+def test_train_with_matrix_set(tr):
+    """fe_train_coeffs with a matrix set: after the fit on the points, refinement steps on the
+    combined objective lower the matrix term; its value, measured by the oracle on the matrices'
+    spectra in FP64, agrees with the kernels' FP32 figure, and the points' error stays at its
+    level."""
+    beta0, mu0, L, n = 20.0, 0.4, 8, 128
+    rng = np.random.default_rng(22)
+    mats = _matrix_set(rng, 4, n, beta0, mu0)
+    dev = [(torch.from_numpy(X0).float().cuda(), torch.from_numpy(D).cuda()) for X0, D in mats]
+    th0, rep0, _ = tr.train_coeffs(L, beta0, mu0, n_points=1024, max_iter=300, tol=1e-12)
+    th, rep, _ = tr.train_coeffs(L, beta0, mu0, n_points=1024, max_iter=300, tol=1e-12,
+                                 mats=dev, mat_iters=30, mat_weight=10.0)
+
+    def oracle_loss(t):
+        s = 0.0
+        for X0, _ in mats:
+            y = np.linalg.eigvalsh(X0)
+            s += float(np.sum((T.forward(y, t) - T.fermi_target(y, beta0, mu0)) ** 2))
+        return s
+    l0, l1 = oracle_loss(th0), oracle_loss(th)
+    e0 = T.max_model_error(th0, beta0, mu0, n=200001)
+    e1 = T.max_model_error(th, beta0, mu0, n=200001)
+    print(f"[matrix set] kernels {rep['mat_loss_start']:.4e} -> {rep['mat_loss_end']:.4e} "
+          f"({rep['mat_accepted']}/{rep['mat_iters']} steps kept); oracle {l0:.4e} -> {l1:.4e}; "
+          f"points max error {e0:.3e} -> {e1:.3e}", flush=True)
+    assert rep["mat_iters"] >= 1
+    assert rep["mat_loss_end"] <= rep["mat_loss_start"]
+    # the kernels evaluate P in FP32 (~1e-7 relative per entry against residuals of ~1e-4)
+    assert rep["mat_loss_start"] == pytest.approx(l0, rel=0.05)
+    assert rep["mat_loss_end"] == pytest.approx(l1, rel=0.05)
+    assert l1 <= l0
+    assert e1 <= 10 * e0

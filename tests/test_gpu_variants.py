@@ -16,6 +16,7 @@ from oracle import fermi as F
 from oracle import recursion as R
 from oracle import variants as V
 from paper_2605_08523_amd import workloads as W
+from parity import within
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +94,17 @@ CASES = [
 ]
 
 
+# measured on MI355X: (||dD||_F/N, max |dD|) against the oracle's matrix recursion
+MEASURED_VARIANTS = {
+    ("max", "dense300"): (6.261e-07, 2.128e-05), ("max", "dense384_flip"): (4.786e-07, 1.558e-05),
+    ("max", "banded700"): (1.810e-07, 1.447e-05), ("max", "anderson512"): (1.907e-07, 4.441e-06),
+    ("skip11", "dense300"): (6.104e-07, 1.991e-05), ("skip11", "dense384_flip"): (3.063e-07, 1.349e-05),
+    ("skip11", "banded700"): (2.489e-07, 1.246e-05), ("skip11", "anderson512"): (1.966e-07, 4.010e-06),
+    ("skip22", "dense300"): (4.866e-07, 1.881e-05), ("skip22", "dense384_flip"): (3.044e-07, 1.603e-05),
+    ("skip22", "banded700"): (2.221e-07, 2.246e-05), ("skip22", "anderson512"): (1.525e-07, 3.887e-06),
+}
+
+
 @pytest.mark.parametrize("family", ["max", "skip11", "skip22"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_density_vs_oracle(var, family, name, make):
@@ -115,10 +127,13 @@ def test_density_vs_oracle(var, family, name, make):
     Dg = D.double().cpu().numpy()
     Dref, oinfo = V.variant_density(H, mu, kT, m, base.beta0, base.mu0)
     fro = np.linalg.norm(Dg - Dref) / n
-    print(f"[{family} {name}] |dD|_F/N={fro:.3e} max={np.max(np.abs(Dg - Dref)):.3e} "
+    mx = np.max(np.abs(Dg - Dref))
+    print(f"[{family} {name}] |dD|_F/N={fro:.3e} max={mx:.3e} "
           f"flipped={info['flipped']}", flush=True)
     assert info["flipped"] == int(oinfo["flipped"])
-    assert fro <= 1e-5
+    meas = MEASURED_VARIANTS[(family, name)]
+    within(f"{family} {name} |dD|_F/N", fro, meas[0], cap=1e-5)
+    within(f"{family} {name} max|dD|", mx, meas[1])
     assert torch.equal(D, D.T)
     assert float(tr) == pytest.approx(np.trace(Dg), rel=1e-9, abs=1e-9)
     assert float(tr2) == pytest.approx(np.sum(Dg * Dg), rel=1e-9)
@@ -145,10 +160,12 @@ def test_embedding_reproduces_mlsp2(var, arch):
     em = np.linalg.norm(Dm.double().cpu().numpy() - exact) / n
     dvm = np.linalg.norm((Dv - Dm).double().cpu().numpy()) / n
     print(f"[embed {arch}] vs exact {ev:.3e} (MLSP2 path {em:.3e}), variant - MLSP2 {dvm:.3e}", flush=True)
-    assert ev <= 1e-5 and dvm <= 1e-6
+    meas = {"max": (5.380e-08, 7.862e-08, 2.313e-04), "skip": (5.355e-08, 7.827e-08, 1.558e-04)}[arch]
+    within(f"embed {arch} vs exact", ev, meas[0], cap=1e-5)
+    within(f"embed {arch} variant - MLSP2", dvm, meas[1])
     print(f"[embed {arch}] |dTrD| variant {abs(float(trv) - ex['trD']):.3e}, "
           f"MLSP2 path {abs(float(trm) - ex['trD']):.3e}", flush=True)
-    assert abs(float(trv) - ex["trD"]) <= 1e-5 * n
+    within(f"embed {arch} |dTrD|", abs(float(trv) - ex["trD"]), meas[2])
 
 
 def test_bf16_traces_only_and_degenerate(var):
@@ -165,7 +182,7 @@ def test_bf16_traces_only_and_degenerate(var):
     Dref, _ = V.variant_density(H, 0.0, 0.2, m, base.beta0, base.mu0)
     fro = np.linalg.norm(D.double().cpu().numpy() - Dref) / 256
     print(f"[bf16] |dD|_F/N={fro:.3e}", flush=True)
-    assert fro <= 1e-4          # BF16 split: 16 significant bits
+    within("bf16 skip21 dense256", fro, 2.042e-05)   # BF16 split: 16 significant bits
     # H = c I: every eigenvalue maps to the same model coordinate; D = f(y) I
     c0 = 0.25
     Hc = torch.full((96, 96), 0.0, dtype=torch.float64).fill_diagonal_(c0).cuda()

@@ -61,7 +61,7 @@ def test_noalloc_rejects_sizes_beyond_the_scratch(api, paper_model):
     H = torch.zeros(16, dtype=torch.float64, device="cuda")   # never read: the size check fails first
     for prec, n in (("fp16x2", 2049), ("fp32", 2305), ("fp64", 1665)):
         rc = lib.fe_expand_density_noalloc(ctypes.c_void_p(H.data_ptr()), n, n, 0.0, 0.1,
-                                           ctypes.byref(m.struct), api.PREC[prec], None, 0, n,
+                                           ctypes.byref(m.struct), api.PREC[prec], 0, None, 0, n,
                                            None, None, None, None)
         assert rc == api.FE_ERR_WORKSPACE, (prec, n, rc)
         assert b"no-allocation scratch" in lib.fe_last_error()
