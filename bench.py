@@ -6,13 +6,15 @@ all L layers (split-precision MFMA products with the fused epilogue) and the FP6
 Workload: 16^3 periodic Anderson lattice (N = 4096), hopping -1, on-site disorder U[-1, 1],
 kT = 0.05, mu = 0. The step selects the model from the bank of trained coefficient sets (fewest
 layers whose region of validity holds the matrix's beta' and mu', Sec. on the region of validity
-by layer count; for this lattice beta' = 280 selects the 22-layer beta0 = 600 model) and then
-expands; the paper's 26-layer (beta0 = 1500, mu0 = 1/3) model is timed beside it.
+by layer count; for this lattice beta' = 280 and mu' = 1/2 select the 20-layer beta0 = 300,
+mu0 = 1/2 model) and then expands; the paper's 26-layer (beta0 = 1500, mu0 = 1/3) model is timed
+beside it, and so are the entropy expansion (the trained entropy model selected the same way)
+and the final correction layer.
 
-Prints one JSON line with the throughput, the roofline of the layer kernel (timed live with HIP
-events on the launch stream), the error against the CPU FP64 eigendecomposition oracle, the
-baselines on the same GPU (plain FP64 recursion with vendor DGEMM, FP64 eigensolver) and the
-oracle timed on the host's cores.
+Prints one JSON line with the throughput, the roofline of the layer kernel (each layer launch
+timed live with HIP events the library records on the launch stream), the error against the CPU
+FP64 eigendecomposition oracle, the baselines on the same GPU (plain FP64 recursion with vendor
+DGEMM, FP64 eigensolver) and the oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -53,9 +55,10 @@ def parse():
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
     p.add_argument("--workload", default="anderson4096",
-                   choices=["anderson4096", "batch1024", "large16384", "filling4096",
+                   choices=["anderson4096", "small128", "batch1024", "large16384", "filling4096",
                             "variants4096", "sweep", "train"],
-                   help="anderson4096: the headline line (default); batch1024: 1024 uneven "
+                   help="anderson4096: the headline line (default); small128: one N = 128 FP64 "
+                        "solve, 30 layers; batch1024: 1024 uneven "
                         "matrices in one captured plan; large16384: one N = 16384 solve, "
                         "density and entropy; filling4096: Newton mu at half filling; "
                         "variants4096: Skip-SP2 / Max-SP2; sweep: ms per D vs N; train: the "
@@ -194,6 +197,8 @@ def main():
         return bench_sweep(args, torch, api, models, workloads, dev)
     if args.workload == "train":
         return bench_train(args, torch, api, models, workloads, dev)
+    if args.workload == "small128":
+        return bench_small(args, torch, api, models, workloads, dev)
     c = workloads.config_anderson_4096()
     H = c["H"]
     n = H.shape[0]
@@ -845,6 +850,67 @@ def bench_variants(args, torch, api, models, workloads, dev):
                         "frac": achieved / PEAK_TFLOPS[args.prec], "traffic": None,
                         "layer_ms": layer_ms,
                         "method": f"HIP events: (t(L={L}) - t(L=1)) / {L - 1}, algorithmic 2 N^3"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_small(args, torch, api, models, workloads, dev):
+    """The small FP64 configuration: N = 128 dense random (seed 0), kT = 0.1, mu for half filling
+    (Tr D = 64, found by the library's Newton iteration in FP64), the 30-layer beta0 = 1500,
+    mu0 = 1/3 model, FP64 products in one workgroup's LDS (`k_small_f64`). One solve per step
+    (launch-latency bound: one CU of 256 works); density and entropy timed."""
+    import numpy as np
+    m = models.load("mlsp2_L30_b1500_mu1third")
+    c = workloads.config_small_dense(0)
+    H, kT = c["H"], c["kT"]
+    n = H.shape[0]
+    Hd = torch.from_numpy(H).to(dev)
+    mref = api.make_model(m.theta, m.beta0, m.mu0)
+    ws = api.Workspace(n)
+    D = torch.empty((n, n), dtype=torch.float64, device=dev)
+    _, mu, iters, _, _, _ = api.expand_density_filling(Hd, c["n_target"], kT, mref, prec="fp64",
+                                                       out_dtype=torch.float64, ws=ws)
+    _, trD, trD2, info = api.expand_density(Hd, mu, kT, mref, prec="fp64", out=D, ws=ws,
+                                            want_info=True)
+    steps = max(args.steps, 200)
+    ms = timed(lambda: api.expand_density(Hd, mu, kT, mref, prec="fp64", out=D, ws=ws), steps,
+               max(args.warmup, 10), torch)
+    ms_s = timed(lambda: api.expand_entropy(Hd, mu, kT, mref, 0.842704, prec="fp64", ws=ws), steps,
+                 max(args.warmup, 10), torch)
+    flop = m.L * 2.0 * n ** 3
+    out = {"metric": "density matrices/s (one N = 128 FP64 solve)", "value": 1000.0 / ms,
+           "unit": "density matrices/s", "n_gpus": 1, "steps": steps, "warmup": max(args.warmup, 10),
+           "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "random_dense_N128_seed0_kT0.1_half_filling", "N": n,
+                      "layers": m.L, "coefficients": m.name, "mu": mu, "newton_iterations": iters,
+                      "beta_p": info["beta_p"]},
+           "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
+           "roofline": {"kernel": "k_small_f64 (whole recursion in one workgroup's LDS)",
+                        "bound": "latency", "achieved": flop / (ms * 1e-3) / 1e12,
+                        "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                        "frac": flop / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+                        "note": "one workgroup on one of the 256 CUs; the step is the launch "
+                                "sequence of bounds, rescale, recursion and reduction"},
+           "entropy_ms": ms_s, "trD": float(trD)}
+    D_g = D.cpu().numpy()
+    if not args.no_cpu_baseline:
+        from oracle import fermi as F
+        lam = np.linalg.eigvalsh(H)
+        mu_ref = F.mu_for_filling(lam, c["n_target"], kT)
+        dts = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            ref = F.density(H, mu_ref, kT)
+            dts.append(time.perf_counter() - t0)
+        dt = sorted(dts)[len(dts) // 2]
+        err = D_g - F.density(H, mu, kT)["D"]
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "density matrices/s", "kind": "oracle",
+                               "cores": os.cpu_count(),
+                               "sample": "the full N = 128 matrix: eigendecomposition + assembly "
+                                         "(FP64, numpy), median of 20 runs"}
+        out["error_vs_oracle"] = {"fro_over_N": float(np.linalg.norm(err) / n),
+                                  "max_abs": float(np.max(np.abs(err))),
+                                  "abs_dTrD": abs(float(trD) - ref["trD"]),
+                                  "abs_dmu": abs(mu - mu_ref)}
     print(json.dumps(out), flush=True)
 
 

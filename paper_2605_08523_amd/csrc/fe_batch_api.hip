@@ -24,6 +24,7 @@ struct fe_batch_plan {
     hipGraphExec_t exec = nullptr;
     fe_workspace* ws = nullptr;
     void* tables = nullptr; // device coefficient tables of both passes
+    void* maps = nullptr;   // device XCD-affine tile maps of the layer launches
     // what a rebuild with another tile size needs (host copies)
     std::vector<fe_batch_item> items;
     std::vector<int> model;
@@ -92,17 +93,54 @@ PassTables make_tables(const std::vector<const fe_model*>& ms, int prec, double 
     return t;
 }
 
-// Enqueues one expansion pass (density or entropy) of the whole batch on `s`. active[l] is the
-// number of tiles of the matrices with more than l layers (a prefix of the sorted batch).
+// XCD-affine tile map of the layer launches over the matrices [0, k) of the sorted batch (those
+// still active): each matrix's tiles go to one XCD, the matrices dealt in batch order to the XCD
+// with the least work so far (work ~ tiles x K length); workgroup 8 i + x takes the i-th tile of
+// XCD x (the hardware deals workgroup g to XCD g % 8 on this 8-XCD chip), empty slots are (-1, -1).
+constexpr int kXcds = 8;
+std::vector<int32_t> xcd_map(const std::vector<fe::BatchMat>& mats, int k, int tile) {
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    for (int m = 0; m < k; ++m) {
+        const int64_t T = mats[m].np / tile, nt = T * (T + 1) / 2;
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+            if (load[y] < load[x]) x = y;
+        load[x] += (double)nt * (double)mats[m].np;
+        for (int64_t t = 0; t < nt; ++t) {
+            lists[x].push_back(m);
+            lists[x].push_back((int32_t)t);
+        }
+    }
+    size_t maxlen = 0;
+    for (const auto& l : lists) maxlen = std::max(maxlen, l.size() / 2);
+    std::vector<int32_t> map(2 * kXcds * maxlen, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t i = 0; i < lists[x].size() / 2; ++i) {
+            map[2 * (kXcds * i + x)] = lists[x][2 * i];
+            map[2 * (kXcds * i + x) + 1] = lists[x][2 * i + 1];
+        }
+    return map;
+}
+
+// One layer launch: its tile map on the device and the number of workgroups.
+struct LayerLaunch {
+    const int32_t* map;
+    int grid;
+};
+
+// Enqueues one expansion pass (density or entropy) of the whole batch on `s`; launches[l] is
+// layer l's launch (grid 0: no matrix has that many layers).
 int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoef& cf,
-                 const std::vector<int>& active, double alpha, int entropy, int bf, int tile,
-                 int32_t* status, hipStream_t s) {
+                 const std::vector<LayerLaunch>& launches, double alpha, int entropy, int bf,
+                 int tile, int32_t* status, hipStream_t s) {
     if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, s));
     FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, cf, bf, s));
     for (int l = 0; l < cf.max_L; ++l) {
-        if (active[l] == 0) break;
+        if (launches[l].grid == 0) break;
         fe::BatchLayerArgs q{};
         q.mats = ws->bmats;
+        q.map = launches[l].map;
         q.count = count;
         q.parity = l & 1;
         q.layer = l;
@@ -110,7 +148,7 @@ int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoe
         q.cf = cf;
         q.P = ws->bparams;
         q.partials = ws->btparts;
-        FE_HIP(fe::launch_batch_layer(q, active[l], bf, tile, s));
+        FE_HIP(fe::launch_batch_layer(q, launches[l].grid, bf, tile, s));
     }
     FE_HIP(fe::launch_batch_reduce(ws->bmats, count, ws->btparts, ws->bparams, entropy, status,
                                    tile, s));
@@ -189,9 +227,11 @@ void release_plan(fe_batch_plan* plan) {
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->tables) (void)hipFree(plan->tables);
+    if (plan->maps) (void)hipFree(plan->maps);
     plan->exec = nullptr;
     plan->graph = nullptr;
     plan->tables = nullptr;
+    plan->maps = nullptr;
 }
 
 // Builds and captures `plan` for its stored inputs with layer tiles of `tile` (128 or 64): item i
@@ -241,7 +281,50 @@ int build_plan(fe_batch_plan* plan, int tile) {
     const std::vector<int> act_e = ent.empty() ? std::vector<int>() : active_tiles(te);
     if (act_d.empty() || (!ent.empty() && act_e.empty()))
         return fail(FE_ERR_ARG, "entropy and density models must order the batch the same way");
+    // active matrices per layer (a prefix), and one XCD-affine map per distinct prefix
+    auto active_mats = [&](const PassTables& t) {
+        std::vector<int> k(t.max_L, 0);
+        for (int l = 0; l < t.max_L; ++l)
+            while (k[l] < count && t.L[mats[k[l]].model] > l) ++k[l];
+        return k;
+    };
+    const std::vector<int> km_d = active_mats(td);
+    const std::vector<int> km_e = ent.empty() ? std::vector<int>() : active_mats(te);
+    std::vector<int> prefixes(km_d.begin(), km_d.end());
+    prefixes.insert(prefixes.end(), km_e.begin(), km_e.end());
+    std::sort(prefixes.begin(), prefixes.end());
+    prefixes.erase(std::unique(prefixes.begin(), prefixes.end()), prefixes.end());
+    std::vector<int32_t> all_maps;
+    std::vector<size_t> map_off(count + 1, 0), map_len(count + 1, 0);
+    for (int k : prefixes) {
+        if (k == 0) continue;
+        const std::vector<int32_t> mp = xcd_map(mats, k, tile);
+        map_off[k] = all_maps.size();
+        map_len[k] = mp.size() / 2;
+        all_maps.insert(all_maps.end(), mp.begin(), mp.end());
+    }
+    // earlier plans on this workspace become stale before its shared descriptors are replaced,
+    // and no launch of them may still be reading those descriptors
+    plan->gen = ++ws->batch_gen;
+    FE_HIP(hipDeviceSynchronize());
     FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
+    {
+        hipError_t em = hipMalloc(&plan->maps, std::max<size_t>(4, all_maps.size() * 4));
+        if (em == hipSuccess && !all_maps.empty())
+            em = hipMemcpy(plan->maps, all_maps.data(), all_maps.size() * 4, hipMemcpyHostToDevice);
+        if (em != hipSuccess) return hip_fail(em, "batch tile maps");
+    }
+    auto launches_of = [&](const std::vector<int>& km) {
+        std::vector<LayerLaunch> v(km.size());
+        for (size_t l = 0; l < km.size(); ++l) {
+            const int k = km[l];
+            v[l].map = k ? static_cast<const int32_t*>(plan->maps) + map_off[k] : nullptr;
+            v[l].grid = k ? (int)map_len[k] : 0;
+        }
+        return v;
+    };
+    const std::vector<LayerLaunch> ll_d = launches_of(km_d);
+    const std::vector<LayerLaunch> ll_e = launches_of(km_e);
 
     plan->tile = tile;
     // device tables: [density coef | L | d0 | shift0 | entropy ...], 256-byte aligned parts
@@ -273,7 +356,6 @@ int build_plan(fe_batch_plan* plan, int tile) {
     if (e == hipSuccess) e = up(eo + ce + le, te.d0.data(), te.d0.size() * 4);
     if (e == hipSuccess) e = up(eo + ce + le + de, te.shift0.data(), te.shift0.size() * 8);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch tables)");
-    plan->gen = ++ws->batch_gen;   // earlier plans on this workspace become stale
     hipStream_t cs;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -281,9 +363,9 @@ int build_plan(fe_batch_plan* plan, int tile) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int bf = prec == FE_PREC_BF16X2;
     if (e == hipSuccess) {
-        rc = enqueue_pass(ws, count, max_np, cfd, act_d, 1.0, 0, bf, tile, status, cs);
+        rc = enqueue_pass(ws, count, max_np, cfd, ll_d, 1.0, 0, bf, tile, status, cs);
         if (rc == FE_OK && !ent.empty())
-            rc = enqueue_pass(ws, count, max_np, cfe, act_e, alpha, 1, bf, tile, status, cs);
+            rc = enqueue_pass(ws, count, max_np, cfe, ll_e, alpha, 1, bf, tile, status, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         plan->graph = g;
@@ -393,6 +475,10 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
     std::iota(order.begin(), order.end(), 0);
     int64_t tiles = 0, max_np = 0;
     std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, 128, &tiles, &max_np);
+    // the descriptors are shared by every plan on the workspace: older plans become stale first,
+    // and none of their launches may still be reading them
+    ++ws->batch_gen;
+    FE_HIP(hipDeviceSynchronize());
     FE_HIP(hipMemcpy(ws->bmats, mats.data(), sizeof(fe::BatchMat) * count, hipMemcpyHostToDevice));
     FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, nullptr));
     std::vector<fe::Params> P(count);
@@ -441,7 +527,10 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
     int rc = FE_OK;
     for (int c = 0; c < 2 && rc == FE_OK && e == hipSuccess; ++c) {
         rc = build_plan(plan, cand[c]);
-        if (rc != FE_OK) break;
+        if (rc != FE_OK) {
+            if (cand[c] != 128) (void)build_plan(plan, 128);   // leave the plan usable
+            break;
+        }
         for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {   // one warm-up, three timed
             if (rep == 1) e = hipEventRecord(e0, s);
             if (e == hipSuccess) e = hipGraphLaunch(plan->exec, s);

@@ -193,6 +193,8 @@ struct BatchCoef {
 };
 struct BatchLayerArgs {
     const BatchMat* mats;
+    const int32_t* map;     // per workgroup (matrix, tile) pairs, (-1, -1) for an empty slot; or
+                            // NULL: workgroup g takes tile g of the grouped grid
     int count;
     int parity;             // hi/lo buffer read by this layer
     int layer;
@@ -206,9 +208,10 @@ constexpr int kBatchPad = 128;   // batch matrices are padded to a multiple of t
 hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s);
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
                                 double alpha, BatchCoef cf, int bf16, hipStream_t s);
-// One layer over the first `active_tiles` tiles of the grouped grid (the matrices whose model
-// has more than q.layer layers come first).
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, int tile,
+// One layer over `grid` workgroups: with q.map, the slots of the map (the tiles of the matrices
+// whose model has more than q.layer layers, each matrix on one XCD); without, the first `grid`
+// tiles of the grouped grid.
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int grid, int bf16, int tile,
                               hipStream_t s);   // tile 128 or 64
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
                                const Params* P, int entropy, int32_t* status, int tile,

@@ -152,26 +152,36 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
     }
 }
 
-// One layer for every upper tile of every matrix. Workgroup g finds its matrix by binary search
-// over the tile prefix sums (matrices sorted by decreasing size, so the longest K loops start
-// first), then runs the same K loop and fused epilogue as the single-matrix kernel.
+// One layer for every upper tile of every matrix, then the same K loop and fused epilogue as the
+// single-matrix kernel. Workgroup g takes the (matrix, tile) of its slot in the plan's map, which
+// keeps all tiles of a matrix on one XCD (the hardware deals workgroup g to XCD g % 8), so the
+// matrix's operand panels are fetched into one L2 instead of eight; without a map it finds its
+// matrix by binary search over the tile prefix sums.
 template <bool BF, class C>
 __global__ void __launch_bounds__(C::NT)
 __attribute__((amdgpu_waves_per_eu(C::BM == 64 ? 4 : 2, C::BM == 64 ? 4 : 2)))
 k_batch_layer(BatchLayerArgs q) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int g = blockIdx.x;
-    int lo = 0, hi = q.count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (q.mats[mid].tile0 <= g) lo = mid;
-        else hi = mid - 1;
+    int lo, t;
+    if (q.map) {
+        lo = q.map[2 * g];
+        t = q.map[2 * g + 1];
+        if (lo < 0) return;   // an empty slot; whole workgroup leaves
+    } else {
+        lo = 0;
+        int hi = q.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.mats[mid].tile0 <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        t = g - q.mats[lo].tile0;
     }
     const BatchMat& m = q.mats[lo];
     const int L = q.cf.L[m.model];
     if (q.layer >= L) return;   // not launched for such matrices; whole workgroup leaves
     const float* cf = q.cf.coef + ((size_t)m.model * q.cf.max_L + q.layer) * 8;
-    const int t = g - m.tile0;
     const int T = (int)(m.np / C::BM);
     int I, J;
     tile_coords(t, T, I, J);
@@ -258,7 +268,7 @@ hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np,
 }
 
 template <bool BF, class C>
-hipError_t launch_layer_t(const BatchLayerArgs& q, int active_tiles, hipStream_t s) {
+hipError_t launch_layer_t(const BatchLayerArgs& q, int grid, hipStream_t s) {
     auto kern = k_batch_layer<BF, C>;
     static bool done = false;
     if (!done) {
@@ -268,18 +278,19 @@ hipError_t launch_layer_t(const BatchLayerArgs& q, int active_tiles, hipStream_t
         if (e != hipSuccess) return e;
         done = true;
     }
-    hipLaunchKernelGGL(kern, dim3(active_tiles), dim3(C::NT), C::LDS_BYTES, s, q);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(C::NT), C::LDS_BYTES, s, q);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_layer(const BatchLayerArgs& q, int active_tiles, int bf16, int tile,
+hipError_t launch_batch_layer(const BatchLayerArgs& q, int grid, int bf16, int tile,
                               hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
     if (tile == 64)
-        return bf16 ? launch_layer_t<true, CfgB64>(q, active_tiles, s)
-                    : launch_layer_t<false, CfgB64>(q, active_tiles, s);
+        return bf16 ? launch_layer_t<true, CfgB64>(q, grid, s)
+                    : launch_layer_t<false, CfgB64>(q, grid, s);
     if (tile != 128) return hipErrorInvalidValue;
-    return bf16 ? launch_layer_t<true, CfgB>(q, active_tiles, s)
-                : launch_layer_t<false, CfgB>(q, active_tiles, s);
+    return bf16 ? launch_layer_t<true, CfgB>(q, grid, s)
+                : launch_layer_t<false, CfgB>(q, grid, s);
 }
 
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,
