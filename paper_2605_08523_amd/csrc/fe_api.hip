@@ -195,6 +195,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = P;
         ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
         ra.X32 = b.X; ra.A32 = b.A; ra.hi = b.hi[0]; ra.lo = b.lo[0];
+        ra.hi1 = b.hi[1]; ra.lo1 = b.lo[1];
         ra.mode = 0; ra.bf16 = bf;
         // squared-affine layers on request (FE_FORM=affine, FP16x2, coefficients permitting);
         // BF16x2 always keeps the FP32 state (its 16-bit split would carry the state alone)

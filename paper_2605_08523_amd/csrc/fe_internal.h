@@ -62,6 +62,8 @@ struct RescaleArgs {
     double* A64;
     uint16_t* hi;
     uint16_t* lo;
+    uint16_t* hi1;      // mode 0, optional: the other operand buffer; its padding (rows or
+    uint16_t* lo1;      // columns >= n), which no layer epilogue writes, is written here too
     int mode;
     int bf16;
     double op_shift;    // mode 0: the hi/lo operand is X0 + op_shift I (squared-affine form)

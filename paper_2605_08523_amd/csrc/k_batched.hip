@@ -1,8 +1,8 @@
 // Batched expansion of many Hamiltonians of uneven size (Alg. 2 applied to each matrix of a
 // batch): batched Gershgorin bounds and rescale parameters, batched rescale/split, one grouped
 // launch per layer covering every upper tile of every matrix, and per-matrix trace reductions.
-// Matrices are padded to multiples of 128; zero padding keeps the padded block decoupled
-// (X stays block diagonal) and the padding is masked out of D and the traces.
+// Matrices are padded to multiples of the tile; the padding is zero off the diagonal, is never
+// rewritten (so X stays block diagonal) and is masked out of D and the traces.
 #include <math.h>
 
 #include "split_common.h"
@@ -149,6 +149,10 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
         split16<BF>(i == j ? (float)(x + s0) : xf, h, l);
         m.hi[0][e] = h;
         m.lo[0][e] = l;
+        if (i >= m.n || j >= m.n) {   // the padding of the other buffer (no epilogue writes it)
+            m.hi[1][e] = h;
+            m.lo[1][e] = l;
+        }
     }
 }
 
@@ -214,8 +218,10 @@ k_batch_layer(BatchLayerArgs q) {
         for (int nb = 0; nb < C::NB; ++nb)
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc.v[mb][nb][j] = 0.0f;
+    // K-blocks wholly in the padding add only zero products to the real block (X is block
+    // diagonal there), and the padded part of the tile is not stored: they are skipped.
     kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
-                    (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
+                 (int)((p.n + C::BK - 1) / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
     epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 

@@ -198,6 +198,10 @@ __global__ void __launch_bounds__(256) k_rescale(RescaleArgs a) {
                 split16<BF>(i == j ? (float)(x + a.op_shift) : xf, h, l);
                 a.hi[e] = h;
                 a.lo[e] = l;
+                if (a.hi1 && (i >= a.n || j >= a.n)) {
+                    a.hi1[e] = h;
+                    a.lo1[e] = l;
+                }
             }
         }
     }

@@ -467,6 +467,10 @@ __device__ inline floatx4 load4_coherent(__amdgpu_buffer_rsrc_t rs, int off) {
 //   accumulate in tr, sq. Diagonal tiles keep only the upper triangle of X and A, and their lower
 //   half of hi/lo (or D) comes from the mirror pass, so every stored matrix is exactly symmetric.
 //   poisoned: every output of the tile is NaN (a stream-K wait gave up).
+//   Padding (rows or columns >= n): four-column groups that lie wholly in it are neither read nor
+//   written, so the padded part of every stored matrix keeps the values the rescale gave it
+//   (zero off the diagonal): X stays block diagonal, and the real block never sees a padded
+//   value. (Groups that straddle n are computed whole: their padded entries come out zero.)
 // Ends with a barrier (sY is free again).
 template <bool BF, class C, int UMAX>
 __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, int J,
@@ -512,13 +516,14 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             const int rl = e / G, c = (e % G) * 4, r = R0 + rl;
             const int loc = r * C::BM + c;
             const int64_t gi = (I0 + r) * np + J0 + c;
+            const bool live = I0 + r < n && J0 + c < n;
             bt.y[u] = Y0 ? *reinterpret_cast<const floatx4*>(Y0 + loc)
                          : *reinterpret_cast<const floatx4*>(sY + rl * C::LDY + c);
             if (nparts > 0)
                 bt.p[u] = load4_coherent(make_rsrc(parts, part_bytes), loc * (int)sizeof(float));
-            if (use_x) bt.x[u] = *reinterpret_cast<const floatx4*>(X + gi);
-            else bt.x[u] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            if (load_a) bt.a[u] = *reinterpret_cast<const floatx4*>(A + gi);
+            const floatx4 z{0.0f, 0.0f, 0.0f, 0.0f};
+            bt.x[u] = (use_x && live) ? *reinterpret_cast<const floatx4*>(X + gi) : z;
+            bt.a[u] = (load_a && live) ? *reinterpret_cast<const floatx4*>(A + gi) : z;
         }
     };
     auto finish_batch = [&](int b0, Batch& bt) {
@@ -549,6 +554,10 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             float* srow = sY + rl * C::LDY + c;
             const int64_t gr = I0 + r, gc = J0 + c;
             const int64_t gi = gr * np + gc;
+            if (!last && (gr >= n || gc >= n)) {   // wholly in the padding: left as it is
+                *reinterpret_cast<floatx4*>(srow) = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                continue;
+            }
             floatx4 xn;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -631,6 +640,7 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             floatx4 v;
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = sY[(rl + k) * C::LDY + c];
+            if (J0 + c >= n || I0 + r >= n) continue;   // wholly in the padding
             const int64_t oi = (J0 + c) * np + I0 + r;
             if (!diag || r + 3 < c) {
                 u32x2 h, l;
