@@ -11,7 +11,13 @@ namespace fe {
 namespace {
 
 using namespace split;
-using CfgB = Cfg<128, 2, 2, 64, 128, 1>;   // same tile and K loop as the data-parallel single-matrix kernel
+// 128 x 128 tiles over eight waves of 32 x 64 (four waves per SIMD with two workgroups per CU):
+// each workgroup's K loop here is short (2 to 12 blocks) and waits on its loads more than on the
+// MFMA pipes, so more waves per CU hide more of that latency (1.08x over four waves of 64 x 64
+// on the batch of 1024); the epilogue keeps two groups of loads in flight per thread (register
+// budget of four waves per SIMD).
+using CfgB = Cfg<128, 4, 2, 64, 128, 1>;
+constexpr int kBatchEpiGroups = 2;
 using CfgB64 = Cfg<64, 2, 2, 32, 64, 1>;   // 64 x 64 tiles (32 x 32 per wave): less padding for small N
 
 __device__ inline double wsum(double v) {
@@ -163,7 +169,7 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
 // matrix by binary search over the tile prefix sums.
 template <bool BF, class C>
 __global__ void __launch_bounds__(C::NT)
-__attribute__((amdgpu_waves_per_eu(C::BM == 64 ? 4 : 2, C::BM == 64 ? 4 : 2)))
+__attribute__((amdgpu_waves_per_eu(4, 4)))
 k_batch_layer(BatchLayerArgs q) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int g = blockIdx.x;
@@ -222,7 +228,7 @@ k_batch_layer(BatchLayerArgs q) {
     // diagonal there), and the padded part of the tile is not stored: they are skipped.
     kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
                  (int)((p.n + C::BK - 1) / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
-    epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
+    epilogue<BF, C, C::BM == 128 ? kBatchEpiGroups : 8>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 
 // Per-matrix fixed-order reduction of the tile traces into Tr, sum of squares, and S (entropy).

@@ -53,10 +53,14 @@ def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch):
         D1, tr1, tr21, _ = api.expand_density(it["H"], it["mu"], it["kT"], m, prec="fp16x2")
         S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec="fp16x2")
         torch.cuda.synchronize()
-        # same tiles, K loop and epilogue as the single-matrix data-parallel kernel: bitwise equal
+        # same tiles, K-block order and epilogue arithmetic as the single-matrix data-parallel
+        # kernel: D bitwise equal, and so is Tr D (an FP64 sum of FP32 values, exact in any
+        # order); sum D^2 and S add FP64 values in an order that follows the workgroup's wave
+        # count (eight waves here, four there), so they agree to FP64 rounding
         assert torch.equal(Db, D1), f"item {b}"
-        assert float(plan.tr[b, 0]) == float(tr1) and float(plan.tr[b, 1]) == float(tr21)
-        assert float(plan.S[b]) == float(S1)
+        assert float(plan.tr[b, 0]) == float(tr1)
+        assert abs(float(plan.tr[b, 1]) - float(tr21)) <= 1e-12 * max(1.0, abs(float(tr21)))
+        assert abs(float(plan.S[b]) - float(S1)) <= 1e-12 * max(1.0, abs(float(S1)))
         Drec, _ = R.mlsp2_density(it["Hn"], it["mu"], it["kT"], m.theta, m.beta0, m.mu0)
         n = Drec.shape[0]
         E = Db.double().cpu().numpy() - Drec
@@ -180,7 +184,7 @@ def test_model_bank_batch(api, monkeypatch, bank_name):
         S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec="fp16x2")
         torch.cuda.synchronize()
         assert torch.equal(plan.D[b], D1), f"item {b}"
-        assert float(plan.S[b]) == float(S1)
+        assert abs(float(plan.S[b]) - float(S1)) <= 1e-12 * max(1.0, abs(float(S1)))   # FP64 sum order
         ref = F.density(it["Hn"], it["mu"], it["kT"])
         n = it["Hn"].shape[0]
         E = plan.D[b].double().cpu().numpy() - ref["D"]
