@@ -60,6 +60,12 @@ extern "C" {
                                (hi*hi, hi*lo, lo*hi) with FP32 accumulation; the lo*lo term is
                                dropped (Sec. V.A, Eq. emulated matmul). FP32 master copy of X. */
 #define FE_PREC_BF16X2  3   /* same with BF16 hi/lo (no lo scaling) */
+#define FE_PREC_BF16X3  4   /* X = hi + mid + lo with BF16 parts (24 significant bits); X^2 from six
+                               BF16 MFMA products (hi*hi, hi*mid, mid*hi, hi*lo, lo*hi, mid*mid)
+                               with FP32 accumulation, the dropped terms below 2^-24 relative
+                               (the split products of Sec. V.A carried to a third part). FP32
+                               master copy of X; data-parallel schedule; not for the variants,
+                               the tuners or fe_expand_density_noalloc. */
 
 /* ---- model: one coefficient table ---------------------------------------------------- */
 typedef struct {
@@ -125,7 +131,7 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
  * expansion) is a static device array of 66 MiB that the library holds on every GPU it runs on
  * until the process ends. Limit: the padded matrices must fit 64 MiB, i.e. n <= 2048 for
  * FE_PREC_FP16X2 / FE_PREC_BF16X2, n <= 2304 for FE_PREC_FP32, n <= 1664 for FE_PREC_FP64;
- * larger n returns FE_ERR_WORKSPACE. Always the data-parallel schedule and the direct layer form.
+ * larger n returns FE_ERR_WORKSPACE; FE_PREC_BF16X3 returns FE_ERR_ARG. Always the data-parallel schedule and the direct layer form.
  * All calls on one GPU share that GPU's array: calls that overlap in time on one GPU (other
  * streams or threads) race and must be serialised by the caller. Arguments, outputs and
  * synchronisation as for fe_expand_density (H, D, trD, trD2 device; info host or NULL),
@@ -206,11 +212,13 @@ typedef struct fe_batch_plan fe_batch_plan;
 
 /* Alg. 2 for every item of a batch (a batch of independent problems; the method is the same as
  * for one matrix). The plan lays the batch out in the workspace (which must have been created
- * with max_batch >= count and batch_elems >= sum of padded sizes squared, padding to multiples
+ * with max_batch >= count and batch_elems >= sum of padded sizes squared (x 20/16 for
+ * FE_PREC_BF16X3, whose arrays take 20 B per element instead of 16), padding to multiples
  * of 128), uploads the descriptors (synchronously) and captures the launch sequence into a HIP
  * graph: batched bounds and rescale, one grouped launch per layer over all upper tiles of all
  * matrices, per-matrix traces, then the entropy pass if mS is not NULL (mS must share beta0 and
- * mu0 with m). Precision: FE_PREC_FP16X2 or FE_PREC_BF16X2. status: device int32[count] or NULL,
+ * mu0 with m). Precision: FE_PREC_FP16X2, FE_PREC_BF16X2 or FE_PREC_BF16X3 (128 x 128 tiles only;
+ * 20 instead of 16 B of the arena per padded element). status: device int32[count] or NULL,
  * receives each item's rescale status (FE_OK, FE_WARN_BETA_CLAMPED, FE_ERR_DOMAIN,
  * FE_ERR_NONFINITE); items with an error get NaN outputs. A workspace holds one batch layout: a
  * new plan makes earlier plans on it stale (their launch returns FE_ERR_WORKSPACE). The items'
@@ -243,7 +251,8 @@ int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
 /* Autotunes the plan's tile size: builds it with each tile size, times three replays of each on
  * `stream` (after a warm-up), keeps the faster. tile (host, may be NULL) receives the choice, ms
  * (host, 2 entries, may be NULL) the ms per replay for tiles 128 and 64. Runs the batch 8 times;
- * waits for the device first and synchronizes. */
+ * waits for the device first and synchronizes. FE_PREC_BF16X3 plans have the 128 x 128 tile only
+ * (ms[1] = NaN; fe_batch_plan_retile to 64 returns FE_ERR_ARG). */
 int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms);
 int fe_batch_plan_destroy(fe_batch_plan* plan);
 

@@ -26,7 +26,7 @@ FE_ERR_NO_CONVERGENCE = -5
 FE_ERR_WORKSPACE = -6
 FE_ERR_RANGE = -7
 
-PREC = {"fp64": 0, "fp32": 1, "fp16x2": 2, "bf16x2": 3}
+PREC = {"fp64": 0, "fp32": 1, "fp16x2": 2, "bf16x2": 3, "bf16x3": 4}
 
 
 class FeError(RuntimeError):
@@ -542,6 +542,8 @@ class BatchPlan:
             np_ = -(-n // 128) * 128
             elems += np_ * np_
         self._items = arr
+        if prec == "bf16x3":   # 20 instead of 16 bytes of the arena per padded element
+            elems = -(-elems * 20 // 16)
         self.ws = ws or Workspace(128, max_batch=self.count, batch_elems=elems)
         p = C.c_void_p()
         self.chosen = None
@@ -577,7 +579,7 @@ class BatchPlan:
         tile = C.c_int32()
         ms = (C.c_double * 2)()
         _check(lib().fe_batch_plan_autotune(self._p, _stream_ptr(), C.byref(tile), ms))
-        return tile.value, {128: ms[0], 64: ms[1]}
+        return tile.value, {t: v for t, v in ((128, ms[0]), (64, ms[1])) if v == v}
 
     def close(self):
         if self._p:

@@ -95,12 +95,13 @@ int use_streamk(int64_t n, const fe_workspace* ws, int prec) {
     return nsk * nk >= 8 * grid ? 2 : 0;
 }
 
-// Slot carving for the precision modes (np x np elements each).
+// Slot carving for the precision modes (np x np elements each). three: the middle parts of the
+// three-part BF16 split follow (20 B per element in all, within the slot's 24).
 struct SplitBufs {
     float *X, *A;
-    uint16_t *hi[2], *lo[2];
+    uint16_t *hi[2], *lo[2], *mid[2];
 };
-SplitBufs carve_split(void* base, int64_t np) {
+SplitBufs carve_split(void* base, int64_t np, bool three = false) {
     SplitBufs b;
     const size_t e = (size_t)np * np;
     b.X = static_cast<float*>(base);
@@ -110,6 +111,8 @@ SplitBufs carve_split(void* base, int64_t np) {
     b.hi[1] = h + e;
     b.lo[0] = h + 2 * e;
     b.lo[1] = h + 3 * e;
+    b.mid[0] = three ? h + 4 * e : nullptr;
+    b.mid[1] = three ? h + 5 * e : nullptr;
     return b;
 }
 struct WideBufs {
@@ -141,10 +144,13 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
     if (rc) return rc;
     rc = check_model(m, entropy ? "entropy model" : "model");
     if (rc) return rc;
-    if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X2) return fail(FE_ERR_ARG, "unknown precision");
+    if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X3) return fail(FE_ERR_ARG, "unknown precision");
+    if (noalloc && prec == FE_PREC_BF16X3)
+        return fail(FE_ERR_ARG, "the entry point without allocation runs FP16x2, BF16x2, FP32 or FP64");
     if (!entropy && D && ldd < n) return fail(FE_ERR_ARG, "ldd < n");
     if (entropy && !(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
-    const bool split = prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2;
+    const bool split = prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2 || prec == FE_PREC_BF16X3;
+    const bool three = prec == FE_PREC_BF16X3;
     if (split && layer_range(m, alpha) > 16.0)
         return fail(FE_ERR_RANGE, "layer values exceed the 16-bit operand range");
 
@@ -180,7 +186,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         FE_HIP(fe::launch_small_f64(sa, s));
     } else if (split) {
         fe::SplitPlan plan{};
-        plan.streamk = use_streamk(n, ws, prec);
+        plan.streamk = three ? 0 : use_streamk(n, ws, prec);   // three parts: data-parallel
         plan.grid = plan.streamk == 2 ? 2 * ws->n_cu : ws->n_cu;
         plan.partial = ws->sk_partial;
         plan.own = ws->sk_partial ? ws->sk_partial + (size_t)ws->n_cu * 256 * 256 : nullptr;
@@ -189,13 +195,14 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
         const int tile = fe::split_tile_for(plan.streamk);
         const int64_t np = round_up(n, tile);
         if (np > ws->np_cap) return fail(FE_ERR_WORKSPACE, "padded size exceeds the workspace");
-        SplitBufs b = carve_split(ws->slot[which], np);
-        const int bf = prec == FE_PREC_BF16X2;
+        SplitBufs b = carve_split(ws->slot[which], np, three);
+        const int bf = three ? 2 : prec == FE_PREC_BF16X2 ? 1 : 0;
         fe::RescaleArgs ra{};
         ra.H = H; ra.n = n; ra.ldh = ldh; ra.np = np; ra.P = P;
         ra.alpha = alpha; ra.mu0 = m->mu0; ra.d0 = dval(0);
         ra.X32 = b.X; ra.A32 = b.A; ra.hi = b.hi[0]; ra.lo = b.lo[0];
         ra.hi1 = b.hi[1]; ra.lo1 = b.lo[1];
+        ra.mid = b.mid[0]; ra.mid1 = b.mid[1]; ra.three = three;
         ra.mode = 0; ra.bf16 = bf;
         // squared-affine layers on request (FE_FORM=affine, FP16x2, coefficients permitting);
         // BF16x2 always keeps the FP32 state (its 16-bit split would carry the state alone)
@@ -220,6 +227,7 @@ int run_expansion(const double* H, int64_t n, int64_t ldh, double mu, double kT,
             la.np = np; la.n = n;
             la.hi_in = b.hi[i & 1]; la.lo_in = b.lo[i & 1];
             la.hi_out = b.hi[(i + 1) & 1]; la.lo_out = b.lo[(i + 1) & 1];
+            la.mid_in = b.mid[i & 1]; la.mid_out = b.mid[(i + 1) & 1];
             la.X = b.X; la.A = b.A;
             if (af.ok) {
                 la.affine = 1;
@@ -404,7 +412,8 @@ int fe_expand_density(const double* H, int64_t n, int64_t ldh, double mu, double
                       fe_rescale_info* info, fe_workspace* ws, void* stream) {
     if (final_correction != 0 && final_correction != 1)
         return fail(FE_ERR_ARG, "final_correction must be 0 or 1");
-    const bool corr = final_correction && (prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2);
+    const bool corr = final_correction &&
+                      (prec == FE_PREC_FP16X2 || prec == FE_PREC_BF16X2 || prec == FE_PREC_BF16X3);
     return run_expansion(H, n, ldh, mu, kT, m, prec, 1.0, 0, D, d_is_fp64, ldd, trD, trD2, nullptr,
                          info, ws, static_cast<hipStream_t>(stream), 0, false, corr);
 }

@@ -155,11 +155,17 @@ int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoe
     return FE_OK;
 }
 
+// Bytes of the arena per padded element: X, A, hi[2], lo[2] (and mid[2] for three parts).
+int64_t arena_bytes_per_elem(int32_t prec) { return prec == FE_PREC_BF16X3 ? 20 : 16; }
+
 // Descriptors of the batch in the arena, in `order`; model[i] is item i's model index.
 std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<int>& order,
                                  const std::vector<int>& model,
                                  const std::vector<const fe_model*>& ms, fe_workspace* ws,
-                                 int64_t bt, int64_t* tiles_out, int64_t* max_np_out) {
+                                 int64_t bt, int32_t prec, int64_t* tiles_out,
+                                 int64_t* max_np_out) {
+    const bool three = prec == FE_PREC_BF16X3;
+    const int64_t bpe = arena_bytes_per_elem(prec);
     const int64_t pad = fe::kBatchPad;
     std::vector<fe::BatchMat> mats(order.size());
     char* arena = static_cast<char*>(ws->arena);
@@ -179,13 +185,15 @@ std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<i
         bm.model = model[order[k]];
         bm.beta0 = ms[bm.model]->beta0;
         bm.mu0 = ms[bm.model]->mu0;
-        bm.X = reinterpret_cast<float*>(arena + off * 16);
+        bm.X = reinterpret_cast<float*>(arena + off * bpe);
         bm.A = bm.X + e;
         uint16_t* h = reinterpret_cast<uint16_t*>(bm.A + e);
         bm.hi[0] = h;
         bm.hi[1] = h + e;
         bm.lo[0] = h + 2 * e;
         bm.lo[1] = h + 3 * e;
+        bm.mid[0] = three ? h + 4 * e : nullptr;
+        bm.mid[1] = three ? h + 5 * e : nullptr;
         bm.D = it.D;
         bm.ldd = it.ldd;
         bm.d_is_fp64 = it.d_is_fp64;
@@ -203,7 +211,7 @@ std::vector<fe::BatchMat> layout(const fe_batch_item* items, const std::vector<i
     return mats;
 }
 
-int check_batch(const fe_batch_item* items, int count, fe_workspace* ws) {
+int check_batch(const fe_batch_item* items, int count, int32_t prec, fe_workspace* ws) {
     if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
     if (!items || count < 1) return fail(FE_ERR_ARG, "empty batch");
     if (count > ws->max_batch) return fail(FE_ERR_WORKSPACE, "batch larger than the workspace's max_batch");
@@ -216,7 +224,8 @@ int check_batch(const fe_batch_item* items, int count, fe_workspace* ws) {
         elems += np * np;
         tiles += T * (T + 1) / 2;
     }
-    if (elems > ws->batch_elems) return fail(FE_ERR_WORKSPACE, "batch exceeds the workspace arena");
+    if (elems * arena_bytes_per_elem(prec) > ws->batch_elems * 16)
+        return fail(FE_ERR_WORKSPACE, "batch exceeds the workspace arena");
     if (tiles > ws->batch_tiles || tiles > (int64_t)0x7fffffff)
         return fail(FE_ERR_WORKSPACE, "batch has too many tiles for the workspace");
     return FE_OK;
@@ -256,7 +265,7 @@ int build_plan(fe_batch_plan* plan, int tile) {
         return items[a].n > items[b].n;
     });
     int64_t tiles = 0, max_np = 0;
-    std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, tile, &tiles, &max_np);
+    std::vector<fe::BatchMat> mats = layout(items, order, model, dens, ws, tile, prec, &tiles, &max_np);
     if (tiles > ws->batch_tiles) return fail(FE_ERR_WORKSPACE, "batch has too many tiles for the workspace");
     const PassTables td = make_tables(dens, prec, 1.0);
     PassTables te;
@@ -361,7 +370,7 @@ int build_plan(fe_batch_plan* plan, int tile) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
     int rc = FE_OK;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    const int bf = prec == FE_PREC_BF16X2;
+    const int bf = prec == FE_PREC_BF16X3 ? 2 : prec == FE_PREC_BF16X2 ? 1 : 0;
     if (e == hipSuccess) {
         rc = enqueue_pass(ws, count, max_np, cfd, ll_d, 1.0, 0, bf, tile, status, cs);
         if (rc == FE_OK && !ent.empty())
@@ -429,10 +438,10 @@ int fe_batch_plan_create(const fe_batch_item* items, int32_t count, const fe_mod
                          fe_workspace* ws, fe_batch_plan** out) {
     if (!out) return fail(FE_ERR_ARG, "out is NULL");
     *out = nullptr;
-    int rc = check_batch(items, count, ws);
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2 && prec != FE_PREC_BF16X3)
+        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2, BF16x2 and BF16x3 modes");
+    int rc = check_batch(items, count, prec, ws);
     if (rc) return rc;
-    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2 and BF16x2 modes");
     rc = check_16bit_model(m, 1.0, "model");
     if (rc) return rc;
     if (mS) {
@@ -454,10 +463,10 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
                               fe_batch_plan** out) {
     if (!out) return fail(FE_ERR_ARG, "out is NULL");
     *out = nullptr;
-    int rc = check_batch(items, count, ws);
+    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2 && prec != FE_PREC_BF16X3)
+        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2, BF16x2 and BF16x3 modes");
+    int rc = check_batch(items, count, prec, ws);
     if (rc) return rc;
-    if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "batched expansion supports the FP16x2 and BF16x2 modes");
     if (!bank || nbank < 1) return fail(FE_ERR_ARG, "empty model bank");
     if (with_entropy && !(fabs(alpha) <= 1.0)) return fail(FE_ERR_ARG, "|alpha| must be <= 1");
     std::vector<const fe_model*> ms;
@@ -474,7 +483,7 @@ int fe_batch_plan_create_bank(const fe_batch_item* items, int32_t count, const f
     std::vector<int> provisional(count, 0), order(count);
     std::iota(order.begin(), order.end(), 0);
     int64_t tiles = 0, max_np = 0;
-    std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, 128, &tiles, &max_np);
+    std::vector<fe::BatchMat> mats = layout(items, order, provisional, ms, ws, 128, prec, &tiles, &max_np);
     // the descriptors are shared by every plan on the workspace: older plans become stale first,
     // and none of their launches may still be reading them
     ++ws->batch_gen;
@@ -511,6 +520,8 @@ int fe_batch_plan_destroy(fe_batch_plan* plan) {
 int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile) {
     if (!plan) return fail(FE_ERR_ARG, "invalid plan");
     if (tile != 64 && tile != 128) return fail(FE_ERR_ARG, "tile must be 64 or 128");
+    if (tile == 64 && plan->prec == FE_PREC_BF16X3)
+        return fail(FE_ERR_ARG, "the three-part BF16 split runs 128 x 128 tiles only");
     FE_HIP(hipDeviceSynchronize());   // a launch of the old graph may still be reading its tables
     return build_plan(plan, tile);
 }
@@ -520,12 +531,13 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
     hipStream_t s = static_cast<hipStream_t>(stream);
     FE_HIP(hipDeviceSynchronize());   // as in fe_batch_plan_retile
     const int cand[2] = {128, 64};
+    const int ncand = plan->prec == FE_PREC_BF16X3 ? 1 : 2;   // three parts: 128 x 128 only
     double t_ms[2] = {0.0, 0.0};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     FE_HIP(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
     int rc = FE_OK;
-    for (int c = 0; c < 2 && rc == FE_OK && e == hipSuccess; ++c) {
+    for (int c = 0; c < ncand && rc == FE_OK && e == hipSuccess; ++c) {
         rc = build_plan(plan, cand[c]);
         if (rc != FE_OK) {
             if (cand[c] != 128) (void)build_plan(plan, 128);   // leave the plan usable
@@ -545,10 +557,10 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "batch autotune");
     if (rc != FE_OK) return rc;
-    const int best = t_ms[1] < t_ms[0] ? 64 : 128;
+    const int best = ncand > 1 && t_ms[1] < t_ms[0] ? 64 : 128;
     if (ms) {
         ms[0] = t_ms[0];
-        ms[1] = t_ms[1];
+        ms[1] = ncand > 1 ? t_ms[1] : NAN;
     }
     if (tile) *tile = best;
     return best == plan->tile ? FE_OK : build_plan(plan, best);

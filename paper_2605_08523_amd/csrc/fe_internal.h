@@ -64,6 +64,9 @@ struct RescaleArgs {
     uint16_t* lo;
     uint16_t* hi1;      // mode 0, optional: the other operand buffer; its padding (rows or
     uint16_t* lo1;      // columns >= n), which no layer epilogue writes, is written here too
+    uint16_t* mid;      // mode 0 with three parts (BF16x3): the middle part, and the other
+    uint16_t* mid1;     // buffer's (padding only)
+    int three;          // mode 0: three-part BF16 split (hi/mid/lo) instead of hi/lo
     int mode;
     int bf16;
     double op_shift;    // mode 0: the hi/lo operand is X0 + op_shift I (squared-affine form)
@@ -75,14 +78,16 @@ hipError_t launch_rescale(const RescaleArgs& a, hipStream_t s);
 // off-diagonal U[-1, 1] / sqrt(n), from a hash of (min(i, j), max(i, j), seed).
 hipError_t launch_fill_symmetric(double* H, int64_t n, uint64_t seed, hipStream_t s);
 
-// One layer of the split-precision (FP16x2 / BF16x2) recursion with the fused epilogue.
+// One layer of the split-precision (FP16x2 / BF16x2 / BF16x3) recursion with the fused epilogue.
 struct LayerArgs {
     int64_t np;             // padded size, multiple of the tile size
     int64_t n;              // real size (for output masking and traces)
     const uint16_t* hi_in;  // current operands (np x np, full symmetric)
     const uint16_t* lo_in;
+    const uint16_t* mid_in; // three-part BF16 split only: the middle part
     uint16_t* hi_out;       // next-layer operands (unused on the last layer)
     uint16_t* lo_out;
+    uint16_t* mid_out;
     float* X;               // FP32 master (upper triangle maintained), in place
     float* A;               // accumulator (upper triangle maintained), in place
     float a, b, c;          // this layer's coefficients
@@ -115,6 +120,7 @@ int split_tile_for(int streamk);
 // The stream-K plan the launcher uses for a padded size np, schedule 1 or 2, at most grid
 // workgroups (host; see streamk_plan.h).
 SkGeometry split_sk_geometry(int64_t np, int streamk, int grid);
+// bf16: 0 FP16x2, 1 BF16x2, 2 three-part BF16 (data-parallel plan only; LayerArgs mid_* set).
 hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s);
 
 // Whole recursion for np <= 128 in FP64 inside one workgroup's LDS. The coefficients travel
@@ -173,6 +179,7 @@ struct BatchMat {
     float* A;
     uint16_t* hi[2];
     uint16_t* lo[2];
+    uint16_t* mid[2];       // three-part BF16 split only
     void* D;
     int64_t ldd;
     int32_t d_is_fp64;
@@ -208,6 +215,7 @@ struct BatchLayerArgs {
 constexpr int kBatchPad = 128;   // batch matrices are padded to a multiple of this
 // Bounds and rescale parameters of every matrix with its own (beta0, mu0).
 hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipStream_t s);
+// bf16 (here and below): 0 FP16x2, 1 BF16x2, 2 three-part BF16 (BatchMat mid[] set; 128 tiles).
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
                                 double alpha, BatchCoef cf, int bf16, hipStream_t s);
 // One layer over `grid` workgroups: with q.map, the slots of the map (the tiles of the matrices

@@ -19,6 +19,9 @@ using namespace split;
 using CfgB = Cfg<128, 4, 2, 64, 128, 1>;
 constexpr int kBatchEpiGroups = 2;
 using CfgB64 = Cfg<64, 2, 2, 32, 64, 1>;   // 64 x 64 tiles (32 x 32 per wave): less padding for small N
+// Three-part BF16 split: the same 128 x 128 tile and eight waves, six panels of 32-deep K-blocks
+// in one LDS stage.
+using CfgB3 = Cfg<128, 4, 2, 32, 128, 1, 0, 3>;
 
 __device__ inline double wsum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -131,7 +134,8 @@ k_batch_bounds(const BatchMat* mats, int count, Params* P) {
 // Rescale and split of every matrix: blockIdx.y selects the matrix, blockIdx.x a chunk.
 template <bool BF>
 __global__ void __launch_bounds__(256)
-k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, BatchCoef cf) {
+k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, BatchCoef cf,
+                int three) {
     const int b = blockIdx.y;
     if (b >= count) return;
     const BatchMat m = mats[b];
@@ -151,11 +155,20 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
         const float xf = (float)x;
         m.X[e] = xf;
         m.A[e] = d0 * xf;
+        const float xs = i == j ? (float)(x + s0) : xf;
+        const bool pad = i >= m.n || j >= m.n;   // the other buffer's padding too (no epilogue writes it)
         uint16_t h, l;
-        split16<BF>(i == j ? (float)(x + s0) : xf, h, l);
+        if (three) {
+            uint16_t md;
+            split3(xs, h, md, l);
+            m.mid[0][e] = md;
+            if (pad) m.mid[1][e] = md;
+        } else {
+            split16<BF>(xs, h, l);
+        }
         m.hi[0][e] = h;
         m.lo[0][e] = l;
-        if (i >= m.n || j >= m.n) {   // the padding of the other buffer (no epilogue writes it)
+        if (pad) {
             m.hi[1][e] = h;
             m.lo[1][e] = l;
         }
@@ -202,6 +215,8 @@ k_batch_layer(BatchLayerArgs q) {
     p.lo_in = m.lo[q.parity];
     p.hi_out = m.hi[q.parity ^ 1];
     p.lo_out = m.lo[q.parity ^ 1];
+    p.mid_in = m.mid[q.parity];
+    p.mid_out = m.mid[q.parity ^ 1];
     p.X = m.X;
     p.A = m.A;
     p.a = cf[0];
@@ -226,8 +241,13 @@ k_batch_layer(BatchLayerArgs q) {
             for (int j = 0; j < 16; ++j) acc.v[mb][nb][j] = 0.0f;
     // K-blocks wholly in the padding add only zero products to the real block (X is block
     // diagonal there), and the padded part of the tile is not stored: they are skipped.
-    kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
-                 (int)((p.n + C::BK - 1) / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
+    const int kend = (int)((p.n + C::BK - 1) / C::BK);
+    if constexpr (C::NS == 3)
+        kloop3<C>(p.hi_in, p.mid_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0, kend,
+                  acc, reinterpret_cast<uint16_t*>(smem));
+    else
+        kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0, kend, acc,
+                     reinterpret_cast<uint16_t*>(smem));
     epilogue<BF, C, C::BM == 128 ? kBatchEpiGroups : 8>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 
@@ -273,9 +293,10 @@ hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np,
     if (chunks > 64) chunks = 64;
     dim3 grid(chunks, count);
     if (bf16)
-        hipLaunchKernelGGL(k_batch_rescale<true>, grid, dim3(256), 0, s, mats, count, P, alpha, cf);
+        hipLaunchKernelGGL(k_batch_rescale<true>, grid, dim3(256), 0, s, mats, count, P, alpha, cf,
+                           bf16 == 2 ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_batch_rescale<false>, grid, dim3(256), 0, s, mats, count, P, alpha, cf);
+        hipLaunchKernelGGL(k_batch_rescale<false>, grid, dim3(256), 0, s, mats, count, P, alpha, cf, 0);
     return hipGetLastError();
 }
 
@@ -297,6 +318,8 @@ hipError_t launch_layer_t(const BatchLayerArgs& q, int grid, hipStream_t s) {
 hipError_t launch_batch_layer(const BatchLayerArgs& q, int grid, int bf16, int tile,
                               hipStream_t s) {
     if (grid < 1) return hipErrorInvalidValue;
+    if (bf16 == 2)   // three-part BF16 split: 128 x 128 tiles only
+        return tile == 128 ? launch_layer_t<true, CfgB3>(q, grid, s) : hipErrorInvalidValue;
     if (tile == 64)
         return bf16 ? launch_layer_t<true, CfgB64>(q, grid, s)
                     : launch_layer_t<false, CfgB64>(q, grid, s);

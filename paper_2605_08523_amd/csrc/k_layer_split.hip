@@ -37,6 +37,9 @@ using namespace split;
 using CfgDP = Cfg<128, 2, 2, 64, 128, 1>;
 using CfgSK = Cfg<256, 2, 4, 32, 128, 2, 1>;   // direct-to-LDS operand staging
 using CfgSK2 = Cfg<128, 2, 2, 64, 128, 1>;   // stream-K over 128 x 128 tiles, two workgroups per CU
+// Three-part BF16 split: six panels of 32-deep K-blocks in one LDS stage (61 KiB), so two
+// workgroups still fit per CU; data-parallel only.
+using CfgDP3 = Cfg<128, 2, 2, 32, 128, 1, 0, 3>;
 
 
 template <class C>
@@ -59,8 +62,12 @@ k_layer_dp(LayerArgs p) {
     tile_coords(t, T, I, J);
     Acc<C> acc;
     zero(acc);
-    kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
-                 (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
+    if constexpr (C::NS == 3)
+        kloop3<C>(p.hi_in, p.mid_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
+                  (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
+    else
+        kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0,
+                     (int)(p.np / C::BK), acc, reinterpret_cast<uint16_t*>(smem));
     epilogue<BF, C>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
 }
 
@@ -165,9 +172,8 @@ hipError_t set_lds(K kern, size_t bytes, bool& done) {
     return e;
 }
 
-template <bool BF>
+template <bool BF, class C = CfgDP>
 hipError_t launch_dp(const LayerArgs& a, hipStream_t s) {
-    using C = CfgDP;
     auto kern = k_layer_dp<BF, C>;
     static bool done = false;
     hipError_t e = set_lds(kern, C::LDS_BYTES, done);
@@ -213,6 +219,7 @@ hipError_t launch_sk(const LayerArgs& a, const SplitPlan& sk, hipStream_t s) {
 }  // namespace
 
 int split_tile_for(int streamk) {
+    static_assert(CfgDP3::BM == CfgDP::BM, "the three-part split runs the data-parallel tile");
     return streamk == 1 ? CfgSK::BM : streamk == 2 ? CfgSK2::BM : CfgDP::BM;
 }
 
@@ -222,6 +229,10 @@ SkGeometry split_sk_geometry(int64_t np, int streamk, int grid) {
 }
 
 hipError_t launch_layer_split(const LayerArgs& a, int bf16, const SplitPlan& plan, hipStream_t s) {
+    if (bf16 == 2) {   // three-part BF16 split: data-parallel schedule only
+        if (plan.streamk != 0) return hipErrorInvalidValue;
+        return launch_dp<true, CfgDP3>(a, s);
+    }
     if (plan.streamk == 1)
         return bf16 ? launch_sk<true, CfgSK>(a, plan, s) : launch_sk<false, CfgSK>(a, plan, s);
     if (plan.streamk == 2)

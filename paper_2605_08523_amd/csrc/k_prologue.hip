@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "fe_internal.h"
+#include "split_common.h"
 
 namespace fe {
 namespace {
@@ -194,11 +195,20 @@ __global__ void __launch_bounds__(256) k_rescale(RescaleArgs a) {
             a.X32[e] = xf;
             a.A32[e] = d0f * xf;
             if (a.mode == 0) {
+                const float xs = i == j ? (float)(x + a.op_shift) : xf;
+                const bool pad = i >= a.n || j >= a.n;
                 uint16_t h, l;
-                split16<BF>(i == j ? (float)(x + a.op_shift) : xf, h, l);
+                if (a.three) {
+                    uint16_t m;
+                    split::split3(xs, h, m, l);
+                    a.mid[e] = m;
+                    if (pad && a.mid1) a.mid1[e] = m;
+                } else {
+                    split16<BF>(xs, h, l);
+                }
                 a.hi[e] = h;
                 a.lo[e] = l;
-                if (a.hi1 && (i >= a.n || j >= a.n)) {
+                if (a.hi1 && pad) {
                     a.hi1[e] = h;
                     a.lo1[e] = l;
                 }

@@ -66,6 +66,35 @@ __device__ inline floatx16 mfma3(u32x4 ahs, u32x4 ah, u32x4 al, u32x4 bh, u32x4 
     return acc;
 }
 
+// Three-part BF16 split (FE_PREC_BF16X3): x = h + m + l with h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m); both differences are exact in FP32, so h + m + l carries 24 significant
+// bits of x (its FP32 value up to the last bit or two).
+__device__ inline void split3(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+    const __bf16 hh = (__bf16)x;
+    const float r1 = x - (float)hh;
+    const __bf16 mm = (__bf16)r1;
+    const float r2 = r1 - (float)mm;
+    const __bf16 ll = (__bf16)r2;
+    h = __builtin_bit_cast(uint16_t, hh);
+    m = __builtin_bit_cast(uint16_t, mm);
+    l = __builtin_bit_cast(uint16_t, ll);
+}
+
+// acc += hh + hm + mh + hl + lh + mm over one 32x32x16 step (six BF16 MFMAs, FP32 accumulate):
+// every product of parts down to 2^-16 of the leading one; the dropped ml, lm, ll are below
+// 2^-24 relative.
+__device__ inline floatx16 mfma6(const u32x4* a, const u32x4* b, floatx16 acc) {
+#define FE_MFMA_BF(x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0)
+    FE_MFMA_BF(a[0], b[0]);
+    FE_MFMA_BF(a[0], b[1]);
+    FE_MFMA_BF(a[1], b[0]);
+    FE_MFMA_BF(a[0], b[2]);
+    FE_MFMA_BF(a[2], b[0]);
+    FE_MFMA_BF(a[1], b[1]);
+#undef FE_MFMA_BF
+    return acc;
+}
+
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -115,10 +144,12 @@ __device__ inline int xcd_tile(int b, int ntiles) {
 
 // Compile-time shape of one kernel configuration. DMA = 1: operands go from global memory straight
 // to LDS (no register staging), in unpadded rows whose 16-byte chunks are XOR-swizzled.
-template <int BM_, int WM_, int WN_, int BK_, int EC_, int STAGES_, int DMA_ = 0>
+// NS = 3: three-part BF16 split (three operand arrays per panel), register-staged loop only.
+template <int BM_, int WM_, int WN_, int BK_, int EC_, int STAGES_, int DMA_ = 0, int NS_ = 2>
 struct Cfg {
     static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_, EC = EC_, STAGES = STAGES_;
     static constexpr int DMA = DMA_;
+    static constexpr int NS = NS_;                    // operand parts (2: hi/lo, 3: hi/mid/lo)
     static constexpr int NT = WM * WN * 64;
     static constexpr int LDK = DMA ? BK : BK + 8;     // LDS row (16-bit elements)
     static constexpr int WAVE_M = BM / WM, WAVE_N = BM / WN;
@@ -126,7 +157,7 @@ struct Cfg {
     static constexpr int CPR = BK / 8;                // 16-byte chunks per panel row
     static constexpr int CH = BM * CPR / NT;          // chunks per thread per array
     static constexpr int LDY = BM + 4;                // epilogue staging row (floats, 16-B aligned)
-    static constexpr size_t STAGE_ELEMS = (size_t)4 * BM * LDK;
+    static constexpr size_t STAGE_ELEMS = (size_t)2 * NS * BM * LDK;
     static constexpr size_t KLOOP_BYTES = STAGES * STAGE_ELEMS * sizeof(uint16_t);
     static constexpr size_t EPI_BYTES = (size_t)EC * LDY * sizeof(float);
     static constexpr size_t LDS_BYTES = KLOOP_BYTES > EPI_BYTES ? KLOOP_BYTES : EPI_BYTES;
@@ -136,6 +167,7 @@ struct Cfg {
     static_assert(EC % 16 == 0 && LDY % 4 == 0, "vectorised epilogue");
     static_assert(!DMA || (STAGES == 2 && BK >= 16 && BK <= 64 && (4 * BM * BK / 512) % (NT / 64) == 0),
                   "direct-to-LDS staging");
+    static_assert(NS == 2 || (NS == 3 && STAGES == 1 && !DMA), "three-part split: one register-staged stage");
 };
 
 // N groups of (M MFMAs, one LDS read) for the scheduler.
@@ -419,6 +451,92 @@ __device__ inline void kloop(const uint16_t* __restrict__ hin, const uint16_t* _
     }
 }
 
+// K loop of the three-part BF16 split (C::NS = 3): acc += the six products of rows I0..I0+BM and
+// rows J0..J0+BM over K blocks [kb0, kb1) of the hi/mid/lo operands (same block order as kloop,
+// so an element's sum does not depend on the tile's wave layout). One LDS stage holding the six
+// BM x BK panels, register prefetch of the next block, one fragment set (register budget).
+// Ends with a barrier.
+template <class C>
+__device__ inline void kloop3(const uint16_t* __restrict__ hin, const uint16_t* __restrict__ min,
+                              const uint16_t* __restrict__ lin, int64_t np, int64_t I0, int64_t J0,
+                              int kb0, int kb1, Acc<C>& acc, uint16_t* smem) {
+    static_assert(C::NS == 3, "three-part split");
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    constexpr int P = C::BM * C::LDK;   // one panel in LDS
+    const uint16_t* src[3] = {hin, min, lin};
+    int64_t goffI[C::CH], goffJ[C::CH];
+    int soff[C::CH];
+#pragma unroll
+    for (int q = 0; q < C::CH; ++q) {
+        const int cidx = tid + q * C::NT;
+        const int row = cidx / C::CPR, kc = cidx % C::CPR;
+        goffI[q] = (I0 + row) * np + kc * 8;
+        goffJ[q] = (J0 + row) * np + kc * 8;
+        soff[q] = row * C::LDK + kc * 8;
+    }
+    u32x4 pA[3][C::CH], pB[3][C::CH];
+    auto gl = [&](int kb) {
+        const int64_t k0 = (int64_t)kb * C::BK;
+#pragma unroll
+        for (int q = 0; q < C::CH; ++q)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                pA[t][q] = *reinterpret_cast<const u32x4*>(src[t] + goffI[q] + k0);
+                pB[t][q] = *reinterpret_cast<const u32x4*>(src[t] + goffJ[q] + k0);
+            }
+    };
+    auto st = [&](uint16_t* buf) {   // panels: A hi, mid, lo, then B hi, mid, lo
+#pragma unroll
+        for (int q = 0; q < C::CH; ++q)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                *reinterpret_cast<u32x4*>(buf + t * P + soff[q]) = pA[t][q];
+                *reinterpret_cast<u32x4*>(buf + (3 + t) * P + soff[q]) = pB[t][q];
+            }
+    };
+    const int frag_row = lane & 31, frag_k = (lane >> 5) * 8;
+    auto compute = [&](const uint16_t* buf) {
+#pragma unroll
+        for (int ks = 0; ks < C::BK / 16; ++ks) {
+            u32x4 fa[C::MB][3], fb[C::NB][3];
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb) {
+                const int o = (wm * C::WAVE_M + mb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) fa[mb][t] = *reinterpret_cast<const u32x4*>(buf + t * P + o);
+            }
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) {
+                const int o = (wn * C::WAVE_N + nb * 32 + frag_row) * C::LDK + ks * 16 + frag_k;
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    fb[nb][t] = *reinterpret_cast<const u32x4*>(buf + (3 + t) * P + o);
+            }
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::NB; ++nb) acc.v[mb][nb] = mfma6(fa[mb], fb[nb], acc.v[mb][nb]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    gl(kb0);
+    st(smem);
+    __syncthreads();
+    for (int kb = kb0; kb < kb1; ++kb) {
+        const bool more = kb + 1 < kb1;
+        if (more) gl(kb + 1);
+        compute(smem);
+        __syncthreads();
+        if (more) {
+            st(smem);
+            __syncthreads();
+        }
+    }
+}
+
 // Four consecutive values split into hi/lo, each packed for one 8-byte store.
 template <bool BF>
 __device__ inline void split4(floatx4 v, u32x2& h, u32x2& l) {
@@ -429,6 +547,49 @@ __device__ inline void split4(floatx4 v, u32x2& h, u32x2& l) {
     split16<BF>(v[3], h3, l3);
     h = u32x2{(unsigned)h0 | ((unsigned)h1 << 16), (unsigned)h2 | ((unsigned)h3 << 16)};
     l = u32x2{(unsigned)l0 | ((unsigned)l1 << 16), (unsigned)l2 | ((unsigned)l3 << 16)};
+}
+
+// Four consecutive values in three BF16 parts, each packed for one 8-byte store.
+__device__ inline void split4x3(floatx4 v, u32x2& h, u32x2& m, u32x2& l) {
+    uint16_t hh[4], mm[4], ll[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) split3(v[k], hh[k], mm[k], ll[k]);
+    h = u32x2{(unsigned)hh[0] | ((unsigned)hh[1] << 16), (unsigned)hh[2] | ((unsigned)hh[3] << 16)};
+    m = u32x2{(unsigned)mm[0] | ((unsigned)mm[1] << 16), (unsigned)mm[2] | ((unsigned)mm[3] << 16)};
+    l = u32x2{(unsigned)ll[0] | ((unsigned)ll[1] << 16), (unsigned)ll[2] | ((unsigned)ll[3] << 16)};
+}
+
+// Next-layer operands of four consecutive elements at `o`: hi/lo, or hi/mid/lo (C::NS = 3).
+template <bool BF, class C>
+__device__ inline void store_split4(const LayerArgs& p, int64_t o, floatx4 v) {
+    if constexpr (C::NS == 3) {
+        u32x2 h, m, l;
+        split4x3(v, h, m, l);
+        *reinterpret_cast<u32x2*>(p.hi_out + o) = h;
+        *reinterpret_cast<u32x2*>(p.mid_out + o) = m;
+        *reinterpret_cast<u32x2*>(p.lo_out + o) = l;
+    } else {
+        u32x2 h, l;
+        split4<BF>(v, h, l);
+        *reinterpret_cast<u32x2*>(p.hi_out + o) = h;
+        *reinterpret_cast<u32x2*>(p.lo_out + o) = l;
+    }
+}
+// ... of one element.
+template <bool BF, class C>
+__device__ inline void store_split1(const LayerArgs& p, int64_t o, float v) {
+    if constexpr (C::NS == 3) {
+        uint16_t h, m, l;
+        split3(v, h, m, l);
+        p.hi_out[o] = h;
+        p.mid_out[o] = m;
+        p.lo_out[o] = l;
+    } else {
+        uint16_t h, l;
+        split16<BF>(v, h, l);
+        p.hi_out[o] = h;
+        p.lo_out[o] = l;
+    }
 }
 
 // Device-coherent (agent scope) 32-bit accesses. Each one is coherent across the XCDs' L2
@@ -496,8 +657,6 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
     constexpr int PER = C::EC * G / C::NT;        // groups per thread in this chunk
     constexpr int U = (PER % 4 == 0 && UMAX >= 4) ? 4 : (PER % 2 == 0 && UMAX >= 2) ? 2 : 1;
     const uint32_t part_bytes = (uint32_t)(C::BM * C::BM * sizeof(float));
-    uint16_t* __restrict__ hout = p.hi_out;
-    uint16_t* __restrict__ lout = p.lo_out;
     const bool load_a = last || upd;
     const bool use_x = p.affine == 0;   // squared-affine form: no FP32 state besides A
 
@@ -573,20 +732,14 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
                             a4[k] = fmaf(dnew, xn[k], fmaf(dold, x[u][k], a[u][k]));
                         *reinterpret_cast<floatx4*>(A + gi) = a4;
                     }
-                    u32x2 h, l;
-                    split4<BF>(xn, h, l);
-                    *reinterpret_cast<u32x2*>(hout + gi) = h;
-                    *reinterpret_cast<u32x2*>(lout + gi) = l;
+                    store_split4<BF, C>(p, gi, xn);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         if (c + k < r) continue;
                         if (use_x) X[gi + k] = xn[k];
                         if (upd) A[gi + k] = fmaf(dnew, xn[k], fmaf(dold, x[u][k], a[u][k]));
-                        uint16_t h, l;
-                        split16<BF>(xn[k], h, l);
-                        hout[gi + k] = h;
-                        lout[gi + k] = l;
+                        store_split1<BF, C>(p, gi + k, xn[k]);
                     }
                 }
                 *reinterpret_cast<floatx4*>(srow) = xn;
@@ -643,18 +796,12 @@ __device__ inline void epi_chunk(const LayerArgs& p, float* sY, int R0, int I, i
             if (J0 + c >= n || I0 + r >= n) continue;   // wholly in the padding
             const int64_t oi = (J0 + c) * np + I0 + r;
             if (!diag || r + 3 < c) {
-                u32x2 h, l;
-                split4<BF>(v, h, l);
-                *reinterpret_cast<u32x2*>(hout + oi) = h;
-                *reinterpret_cast<u32x2*>(lout + oi) = l;
+                store_split4<BF, C>(p, oi, v);
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (r + k >= c) continue;
-                    uint16_t h, l;
-                    split16<BF>(v[k], h, l);
-                    p.hi_out[oi + k] = h;
-                    p.lo_out[oi + k] = l;
+                    store_split1<BF, C>(p, oi + k, v[k]);
                 }
             }
         }

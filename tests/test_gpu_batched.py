@@ -39,19 +39,26 @@ MEASURED_BATCH12 = [1.215e-07, 1.160e-07, 2.853e-07, 2.305e-07, 1.273e-07, 6.448
                     1.708e-07, 2.440e-07, 1.146e-07, 1.676e-07, 1.236e-07]
 
 
-def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch):
+# the same with the three-part BF16 split
+MEASURED_BATCH12_BF16X3 = [1.495e-07, 1.269e-07, 3.231e-07, 2.792e-07, 1.451e-07, 7.094e-08,
+                           1.682e-07, 1.786e-07, 2.390e-07, 1.300e-07, 1.781e-07, 1.412e-07]
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x3"])
+def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch, prec):
     m = paper_model
     mats = uneven_batch(12, 500)
-    print("case batch12 fp16x2", flush=True)
-    plan = api.BatchPlan(mats, m, prec="fp16x2", model_s=m, alpha=0.842704)
+    print(f"case batch12 {prec}", flush=True)
+    plan = api.BatchPlan(mats, m, prec=prec, model_s=m, alpha=0.842704)
     plan.launch()
     torch.cuda.synchronize()
     assert plan.status.cpu().numpy().tolist() == [0] * 12
     monkeypatch.setenv("FE_SCHEDULE", "dp")
+    measured = MEASURED_BATCH12 if prec == "fp16x2" else MEASURED_BATCH12_BF16X3
     for b, it in enumerate(mats):
         Db = plan.D[b]
-        D1, tr1, tr21, _ = api.expand_density(it["H"], it["mu"], it["kT"], m, prec="fp16x2")
-        S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec="fp16x2")
+        D1, tr1, tr21, _ = api.expand_density(it["H"], it["mu"], it["kT"], m, prec=prec)
+        S1, _ = api.expand_entropy(it["H"], it["mu"], it["kT"], m, 0.842704, prec=prec)
         torch.cuda.synchronize()
         # same tiles, K-block order and epilogue arithmetic as the single-matrix data-parallel
         # kernel: D bitwise equal, and so is Tr D (an FP64 sum of FP32 values, exact in any
@@ -66,7 +73,7 @@ def test_batch_matches_single_and_oracle(api, paper_model, monkeypatch):
         E = Db.double().cpu().numpy() - Drec
         fro = np.linalg.norm(E) / n
         print(f"[batch item {b}] N={n} |dD|_F/N={fro:.3e} max|dD|={np.max(np.abs(E)):.3e}", flush=True)
-        within(f"batch item {b}", fro, MEASURED_BATCH12[b], cap=1e-5)
+        within(f"batch item {b} {prec}", fro, measured[b], cap=1e-5)
 
 
 def test_batch_status_errors_and_replay(api, paper_model):
@@ -240,3 +247,18 @@ def test_batch_tile_64_and_autotune(api, paper_model):
     for b in range(16):
         assert float((plan.D[b] - D128[b]).abs().max()) < 1e-4
     plan.close()
+
+
+def test_bf16x3_plan_tiles(api, paper_model):
+    """A three-part BF16 plan has the 128 x 128 tile only: the tuner times that one and keeps it,
+    and a retile to 64 is refused."""
+    mats = uneven_batch(3, 900)
+    plan = api.BatchPlan(mats, paper_model, prec="bf16x3")
+    tile, ms = plan.autotune()
+    assert tile == 128 and set(ms) == {128}
+    with pytest.raises(api.FeError) as e:
+        plan.retile(64)
+    assert e.value.code == api.FE_ERR_ARG
+    plan.launch()
+    torch.cuda.synchronize()
+    assert plan.status.cpu().numpy().tolist() == [0] * 3

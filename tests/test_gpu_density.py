@@ -94,10 +94,16 @@ MEASURED_SPLIT = {
     ("dense1000", "bf16x2"): (3.109e-06, 2.628e-04, 1.117e-02),
     ("banded700", "fp16x2"): (1.164e-07, 1.108e-05, 5.288e-04),
     ("banded700", "bf16x2"): (2.554e-06, 2.504e-04, 2.190e-03),
+    ("dense128", "bf16x3"): (3.421e-07, 6.659e-06, 1.248e-04),
+    ("dense200_noflip", "bf16x3"): (2.511e-07, 6.191e-06, 1.684e-04),
+    ("dense384", "bf16x3"): (1.657e-07, 6.873e-06, 1.849e-04),
+    ("anderson512", "bf16x3"): (1.749e-07, 3.513e-06, 4.886e-04),
+    ("dense1000", "bf16x3"): (1.647e-07, 1.742e-05, 1.038e-03),
+    ("banded700", "bf16x3"): (1.146e-07, 9.566e-06, 5.744e-04),
 }
 
 
-@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2", "bf16x3"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_split_modes_against_oracle(api, paper_model, prec, name, make):
     m = paper_model
@@ -140,8 +146,9 @@ def test_anderson_4096_fp16x2(api, paper_model):
     Hd = torch.from_numpy(c["H"]).cuda()
     k = api.select_model(Hd, c["mu"], c["kT"], bank)
     assert bench.BANK[k] == "mlsp2_L20_b300_mu0p5"
-    measured = {"fp16x2": (2.400e-08, 2.864e-06, 1.042e-03), "bf16x2": (3.531e-07, 4.468e-05, 2.175e-03)}
-    for prec in ("fp16x2", "bf16x2"):
+    measured = {"fp16x2": (2.400e-08, 2.864e-06, 1.042e-03), "bf16x2": (3.531e-07, 4.468e-05, 2.175e-03),
+                "bf16x3": (2.416e-08, 4.295e-06, 1.971e-04)}
+    for prec in ("fp16x2", "bf16x2", "bf16x3"):
         print(f"case anderson4096 {prec} bank model {bench.BANK[k]}", flush=True)
         D, tr, tr2, info, Dt = run(api, c["H"], c["mu"], c["kT"], bank[k], prec)
         assert info["rc"] == 0
@@ -159,7 +166,8 @@ def test_anderson_4096_fp16x2(api, paper_model):
                            trc, exact["trD"])
         check_errors(f"anderson4096 {prec} bank final correction", froc, mxc,
                      {"fp16x2": (2.832e-08, 4.838e-06, 3.253e-03),
-                      "bf16x2": (3.518e-07, 4.638e-05, 1.337e-03)}[prec], abs(trc - exact["trD"]))
+                      "bf16x2": (3.518e-07, 4.638e-05, 1.337e-03),
+                      "bf16x3": (2.625e-08, 6.197e-06, 2.022e-03)}[prec], abs(trc - exact["trD"]))
         assert torch.equal(Dct, Dct.T)
         assert not torch.equal(Dct, Dct.float().double()), "an FP64 D, not FP32 values"
         assert trc == pytest.approx(np.trace(Dc), abs=1e-9 * 4096)
@@ -273,7 +281,7 @@ def test_rescale_parity(api, paper_model):
         assert info["flipped"] == int(oinfo["flipped"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2", "bf16x3"])
 def test_entropy_against_oracle(api, paper_model, prec):
     m = paper_model
     alpha = 0.842704
@@ -288,7 +296,8 @@ def test_entropy_against_oracle(api, paper_model, prec):
     if prec == "fp64":
         assert abs(S - Srec) <= 1e-10 * abs(Srec)
     else:
-        within("entropy fp16x2 relative", abs(S - Srec) / abs(Srec), 3.184e-06)
+        within(f"entropy {prec} relative", abs(S - Srec) / abs(Srec),
+               {"fp16x2": 3.184e-06, "bf16x3": 6.010e-06}[prec])
 
 
 # n = 5700 hybrid schedule against the oracle: 10x the measured ||dD||_F/N (2.48e-8), max |dD|
@@ -556,3 +565,19 @@ def test_layer_forms_agree(api, sk_ws, paper_model, monkeypatch, sch):
           f"{abs(out['affine'][1] - out['mlsp2'][1]):.3e}", flush=True)
     assert d < 1e-4
     assert out["affine"][1] == pytest.approx(out["mlsp2"][1], rel=1e-4, abs=1e-3)
+
+
+def test_bf16x3_argument_limits(api, paper_model):
+    """The three-part BF16 split runs the data-parallel schedule only: the tuners, the entry point
+    without allocation and the Skip-SP2 / Max-SP2 family reject it with FE_ERR_ARG; an expansion
+    under a forced stream-K schedule still runs (data-parallel)."""
+    H = torch.from_numpy(W.random_dense(256, 3)).cuda()
+    for call in (lambda: api.expand_density_noalloc(H, 0.0, 0.1, paper_model, prec="bf16x3"),
+                 lambda: api.autotune([1024], prec="bf16x3")):
+        with pytest.raises(api.FeError) as e:
+            call()
+        assert e.value.code == api.FE_ERR_ARG
+    from paper_2605_08523_amd import variants as V
+    with pytest.raises(api.FeError) as e:
+        V.expand_density_variant(H, 0.0, 0.1, V.embed_mlsp2(paper_model, "skip"), prec="bf16x3")
+    assert e.value.code == api.FE_ERR_ARG

@@ -34,6 +34,42 @@ MEASURED_1024 = {211: (7.545e-07, 5.766e-05), 61: (1.753e-06, 1.924e-03), 649: (
 MEASURED_1024_BANK = {211: 2.661e-07, 61: 5.677e-08, 649: 1.886e-07, 661: 9.318e-08, 804: 9.188e-08}
 
 
+# the batch in the three-part BF16 split (single-model plan), same sample: (||dD||_F/N, |dTr D|)
+MEASURED_1024_BF16X3 = {211: (4.397e-07, 1.627e-05), 61: (1.369e-06, 1.427e-03),
+                        649: (1.116e-06, 1.559e-04), 661: (2.730e-07, 6.754e-04),
+                        804: (8.505e-07, 1.542e-03)}
+
+
+def test_batch1024_bf16x3_sampled_against_oracle(api):
+    """The batch in BF16 arithmetic: the three-part split meets the bar where the two-part BF16
+    split does not (beta' up to ~3700)."""
+    m = models.load("mlsp2_L40_b1e4_mu1third")
+    items = W.batch_items(1024, 2000)
+    mats = [dict(H=torch.from_numpy(it["H"]).cuda(), mu=it["mu"], kT=it["kT"]) for it in items]
+    print("case batch1024 bf16x3", flush=True)
+    plan = api.BatchPlan(mats, m, prec="bf16x3")
+    plan.launch()
+    torch.cuda.synchronize()
+    assert int(np.count_nonzero(plan.status.cpu().numpy())) == 0
+    ns = np.array([it["n"] for it in items])
+    order = np.argsort(ns, kind="stable")
+    rng = np.random.default_rng(77)
+    sample = [int(order[0]), int(order[-1])] + [int(b) for b in rng.choice(1024, 3, replace=False)]
+    for b in sample:
+        it = items[b]
+        ref = F.density(it["H"], it["mu"], it["kT"])
+        Dg = plan.D[b].double().cpu().numpy()
+        n = it["n"]
+        fro = np.linalg.norm(Dg - ref["D"]) / n
+        dtr = abs(float(plan.tr[b, 0]) - ref["trD"])
+        print(f"[batch1024 bf16x3 item {b}] N={n} kT={it['kT']:.3f} |dD|_F/N={fro:.3e} "
+              f"max|dD|={np.max(np.abs(Dg - ref['D'])):.3e} |dTrD|={dtr:.3e}", flush=True)
+        within(f"batch1024 bf16x3 item {b} |dD|_F/N", fro, MEASURED_1024_BF16X3[b][0], cap=1e-5)
+        within(f"batch1024 bf16x3 item {b} |dTrD|", dtr, MEASURED_1024_BF16X3[b][1])
+        assert np.array_equal(Dg, Dg.T)
+    plan.close()
+
+
 def test_batch1024_sampled_against_oracle(api):
     m = models.load("mlsp2_L40_b1e4_mu1third")
     items = W.batch_items(1024, 2000)
