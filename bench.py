@@ -456,8 +456,9 @@ def main():
 def bench_batch(args, torch, api, models, workloads, dev):
     """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (grouped per-layer launches in a
     hipGraph; its layer tile, 128 x 128 or 64 x 64, chosen by the plan's autotuner), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
-    1e-5 bar on this batch: beta' reaches ~3700). Sampled items are checked against the CPU
-    oracle (eigendecomposition) in the cpu_baseline leg."""
+    1e-5 bar on this batch: beta' reaches ~3700; --prec bf16x3, the three-part BF16 split, meets
+    it). Sampled items are checked against the CPU oracle (eigendecomposition) in the
+    cpu_baseline leg."""
     import numpy as np
     m = models.load("mlsp2_L40_b1e4_mu1third")
     t0 = time.perf_counter()
