@@ -76,7 +76,7 @@ int fe_expand_density_variant(const double* H, int64_t n, int64_t ldh, double mu
     rc = check_qmodel(m);
     if (rc) return rc;
     if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "the Skip-SP2 / Max-SP2 path runs the 16-bit split modes only");
+        return fail(FE_ERR_ARG, "the Skip-SP2 / Max-SP2 path runs the two-part 16-bit split modes only");
     if (D && ldd < n) return fail(FE_ERR_ARG, "ldd < n");
     const int64_t np = round_up(n, kVarTile);
     const int slots = square_slots();
