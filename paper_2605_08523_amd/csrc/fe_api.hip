@@ -570,7 +570,7 @@ int fe_autotune_input(const double* H, int64_t n, int64_t ldh, double mu, double
                       const fe_model* m, int32_t prec, int32_t* choice, double* ms,
                       fe_workspace* ws, void* stream) {
     if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "the tuner chooses among the two-part 16-bit split schedules");
+        return fail(FE_ERR_ARG, "the tuner chooses among the 16-bit split schedules");
     int rc = check_common(H, n, ldh, mu, kT, ws);
     if (rc) return rc;
     rc = check_model(m, "model");
@@ -587,7 +587,7 @@ int fe_autotune(const int64_t* sizes, int32_t count, int32_t prec, int32_t* choi
     if (!sizes || count < 1) return fail(FE_ERR_ARG, "no sizes to tune");
     if (!ws) return fail(FE_ERR_ARG, "workspace is NULL");
     if (prec != FE_PREC_FP16X2 && prec != FE_PREC_BF16X2)
-        return fail(FE_ERR_ARG, "the tuner chooses among the two-part 16-bit split schedules");
+        return fail(FE_ERR_ARG, "the tuner chooses among the 16-bit split schedules");
     int64_t nmax = 0;
     for (int i = 0; i < count; ++i) {
         if (sizes[i] < 1) return fail(FE_ERR_ARG, "sizes must be >= 1");
@@ -830,8 +830,6 @@ extern "C" int fe_expand_density_noalloc(const double* H, int64_t n, int64_t ldh
     if (n < 1) return fail(FE_ERR_ARG, "n must be >= 1");
     if (final_correction != 0 && final_correction != 1)
         return fail(FE_ERR_ARG, "final_correction must be 0 or 1");
-    if (prec == FE_PREC_BF16X3)
-        return fail(FE_ERR_ARG, "the three-part BF16 split is not available without allocation");
     if (prec < FE_PREC_FP64 || prec > FE_PREC_BF16X2) return fail(FE_ERR_ARG, "unknown precision");
     if (n > ((int64_t)1 << 16) || expansion_slot_bytes(n, prec) > kNoAllocSlotBytes)
         return fail(FE_ERR_WORKSPACE, "n exceeds the no-allocation scratch (64 MiB of matrices: "
