@@ -52,6 +52,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--prec", default="fp16x2", choices=["fp16x2", "bf16x2", "bf16x3"],
                    help="bf16x3 (three-part BF16 split, six products): batch1024 only")
+    p.add_argument("--batch-launch", default="queue", choices=["queue", "layers"],
+                   help="batch1024: every layer in one queue launch (default), or one grouped "
+                        "launch per layer")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
@@ -454,8 +457,10 @@ def main():
 
 
 def bench_batch(args, torch, api, models, workloads, dev):
-    """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (grouped per-layer launches in a
-    hipGraph; its layer tile, 128 x 128 or 64 x 64, chosen by the plan's autotuner), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
+    """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (a hipGraph: bounds, rescale, every
+    layer of every matrix in one queue launch (--batch-launch layers: one grouped launch per layer,
+    the other form timed beside it), traces; its layer tile, 128 x 128 or 64 x 64, chosen by the
+    plan's autotuner), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
     1e-5 bar on this batch: beta' reaches ~3700; --prec bf16x3, the three-part BF16 split, meets
     it). Sampled items are checked against the CPU oracle (eigendecomposition) in the
     cpu_baseline leg."""
@@ -468,6 +473,10 @@ def bench_batch(args, torch, api, models, workloads, dev):
     prec = args.prec
     plan = api.BatchPlan(mats, m, prec=prec)
     tile, tile_ms = plan.autotune()
+    other = "queue" if args.batch_launch == "layers" else "layers"
+    plan.set_launch(other)
+    ms_other = timed(plan.launch, args.steps, args.warmup, torch)
+    plan.set_launch(args.batch_launch)
     ms = timed(plan.launch, args.steps, args.warmup, torch)
     status = plan.status.cpu().numpy()
     ns = np.array([it["n"] for it in items], dtype=np.float64)
@@ -482,13 +491,17 @@ def bench_batch(args, torch, api, models, workloads, dev):
                       "precision": prec},
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "status_nonzero": int(np.count_nonzero(status)),
-           "tile_autotune": {"tile": tile, "ms_per_step": {str(k): v for k, v in tile_ms.items()}}}
+           "tile_autotune": {"tile": tile, "ms_per_step": {str(k): v for k, v in tile_ms.items()}},
+           "launch": {"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms, other: ms_other}}}
     # the same batch over the model bank: each matrix runs the fewest layers valid for it
     bank_names = BANK
     bank = [models.load(x) for x in bank_names]
     plan.close()
     bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)
     tile_b, tile_ms_b = bplan.autotune()
+    bplan.set_launch(other)
+    ms_b_other = timed(bplan.launch, args.steps, args.warmup, torch)
+    bplan.set_launch(args.batch_launch)
     ms_b = timed(bplan.launch, args.steps, args.warmup, torch)
     Ls = np.array([bank[k].L for k in bplan.chosen], dtype=np.float64)
     out["model_bank"] = {
@@ -497,7 +510,8 @@ def bench_batch(args, torch, api, models, workloads, dev):
         "items_per_model": [int(np.sum(bplan.chosen == k)) for k in range(len(bank))],
         "tflops_algorithmic": float(np.sum(Ls * 2.0 * ns ** 3)) / (ms_b * 1e-3) / 1e12,
         "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy())),
-        "tile_autotune": {"tile": tile_b, "ms_per_step": {str(k): v for k, v in tile_ms_b.items()}}}
+        "tile_autotune": {"tile": tile_b, "ms_per_step": {str(k): v for k, v in tile_ms_b.items()}},
+        "launch": {"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms_b, other: ms_b_other}}}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         order = np.argsort(ns)

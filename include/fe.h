@@ -215,8 +215,8 @@ typedef struct fe_batch_plan fe_batch_plan;
  * with max_batch >= count and batch_elems >= sum of padded sizes squared (x 20/16 for
  * FE_PREC_BF16X3, whose arrays take 20 B per element instead of 16), padding to multiples
  * of 128), uploads the descriptors (synchronously) and captures the launch sequence into a HIP
- * graph: batched bounds and rescale, one grouped launch per layer over all upper tiles of all
- * matrices, per-matrix traces, then the entropy pass if mS is not NULL (mS must share beta0 and
+ * graph: batched bounds and rescale, the layers (all in one queue launch, or one grouped launch
+ * per layer: fe_batch_plan_set_launch), per-matrix traces, then the entropy pass if mS is not NULL (mS must share beta0 and
  * mu0 with m). Precision: FE_PREC_FP16X2, FE_PREC_BF16X2 or FE_PREC_BF16X3 (128 x 128 tiles only;
  * 20 instead of 16 B of the arena per padded element). status: device int32[count] or NULL,
  * receives each item's rescale status (FE_OK, FE_WARN_BETA_CLAMPED, FE_ERR_DOMAIN,
@@ -247,6 +247,25 @@ int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
  * the order of FP32 sums. Waits for the device first (a launch of the plan may be in flight), then
  * replaces the captured graph; on failure the plan is left empty and its launches fail. */
 int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
+
+/* How a plan runs the layers of a pass. FE_BATCH_LAUNCH_QUEUE (the default): every layer of every
+ * matrix in one launch: each matrix's (tile, layer) work items sit in the queue of one XCD in
+ * layer-major order; a workgroup takes the next item of its XCD's queue and starts it once the
+ * matrix has completed its previous layer (bounded waits; the XCD is read from the hardware, so
+ * the L2 that holds the matrix is the one its readers use). It needs the device to deal
+ * workgroups to its XCDs round-robin, which a probe launch checks once per device; where that
+ * fails, plans fall back to FE_BATCH_LAUNCH_LAYERS: one grouped launch per layer over all upper
+ * tiles of all matrices. Both forms run the same per-tile arithmetic in the same order, so they
+ * give bitwise equal results. If a wait gives up (it never should: every wait is on earlier items of
+ * the same queue, all held by running workgroups), the matrix's outputs are NaN and its status
+ * FE_ERR_HIP. The queue launch holds 16 B of device tables per work item (upper tiles x layers,
+ * summed over the matrices and both passes), allocated with the plan. */
+#define FE_BATCH_LAUNCH_LAYERS 0
+#define FE_BATCH_LAUNCH_QUEUE  1
+/* Rebuilds the plan with the given launch form (keeping its tile size); waits for the device
+ * first, as fe_batch_plan_retile, and likewise leaves the plan empty on failure. FE_ERR_ARG for
+ * FE_BATCH_LAUNCH_QUEUE where the device probe failed (the plan is then left as it was). */
+int fe_batch_plan_set_launch(fe_batch_plan* plan, int32_t launch);
 
 /* Autotunes the plan's tile size: builds it with each tile size, times three replays of each on
  * `stream` (after a warm-up), keeps the faster. tile (host, may be NULL) receives the choice, ms
@@ -482,6 +501,13 @@ int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, i
  * as a wait that timed out would. Every kernel still exits normally; the tiles finished after a
  * give-up are NaN, the traces NaN, and the rescale info status FE_ERR_HIP. */
 int fe_debug_streamk_giveup(int32_t enable);
+
+/* Test hook for failure handling (process-wide), the same for the batch queue launch
+ * (FE_BATCH_LAUNCH_QUEUE): batch plans built while it is enabled wait, for every work item, for a
+ * completion count that no matrix reaches; the first wait gives up after a short bounded spin and
+ * the rest at once. Every kernel still exits normally; every matrix of such a plan gets NaN
+ * outputs and status FE_ERR_HIP. */
+int fe_debug_batch_queue_giveup(int32_t enable);
 
 /* Per-launch timing of the layer kernel with HIP events on the call's stream (process-wide; for
  * the roofline measurement of Sec. V.A's layer product): while enabled, every expansion on the

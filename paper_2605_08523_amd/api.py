@@ -86,6 +86,7 @@ SIGNATURES = {
     "fe_matrix_backward": (_I32, [_P, _I64, _P, _I32, _P, _P, _P, _I32, _P, _P]),
     "fe_layer_count": (_D, [_D]),
     "fe_batch_plan_retile": (_I32, [_P, _I32]),
+    "fe_batch_plan_set_launch": (_I32, [_P, _I32]),
     "fe_batch_plan_autotune": (_I32, [_P, _P, C.POINTER(_I32), C.POINTER(_D)]),
     "fe_autotune": (_I32, [C.POINTER(_I64), _I32, _I32, C.POINTER(_I32), C.POINTER(_D), _P, _P]),
     "fe_autotune_input": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, C.POINTER(_I32),
@@ -105,6 +106,7 @@ SIGNATURES = {
     "fe_streamk_segments": (_I32, [_I64, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), _I32,
                                    C.POINTER(_I32)]),
     "fe_debug_streamk_giveup": (_I32, [_I32]),
+    "fe_debug_batch_queue_giveup": (_I32, [_I32]),
     "fe_debug_layer_events": (_I32, [_I32]),
     "fe_debug_layer_events_read": (_I32, [C.POINTER(_D), _I32, C.POINTER(_I32)]),
     "fe_last_error": (C.c_char_p, []),
@@ -483,6 +485,12 @@ def debug_streamk_giveup(enable: bool) -> None:
     _check(lib().fe_debug_streamk_giveup(1 if enable else 0))
 
 
+def debug_batch_queue_giveup(enable: bool) -> None:
+    """fe_debug_batch_queue_giveup: batch plans built while enabled make every queue-launch wait
+    give up (failure-handling tests)."""
+    _check(lib().fe_debug_batch_queue_giveup(1 if enable else 0))
+
+
 # ---- batches -----------------------------------------------------------------------------
 
 class fe_batch_item(C.Structure):
@@ -504,8 +512,12 @@ SIGNATURES.update({
 })
 
 
+BATCH_LAUNCH = {"layers": 0, "queue": 1}   # FE_BATCH_LAUNCH_*
+
+
 class BatchPlan:
     """A captured batch (fe_batch_plan_create): `launch()` replays it on the current stream.
+    By default every layer of every matrix runs in one queue launch (`set_launch`).
 
     Each entry of `mats` is a dict with keys H (float64 device tensor), mu, kT. Outputs are
     allocated here: D (float32, or float64 with d_dtype), traces tr[b] = (Tr D, sum D_ij^2), S[b]
@@ -573,6 +585,11 @@ class BatchPlan:
     def retile(self, tile: int):
         """fe_batch_plan_retile: rebuild with 128 x 128 or 64 x 64 layer tiles."""
         _check(lib().fe_batch_plan_retile(self._p, int(tile)))
+
+    def set_launch(self, launch: str):
+        """fe_batch_plan_set_launch: "layers" (one grouped launch per layer) or "queue" (every
+        layer of every matrix in one launch)."""
+        _check(lib().fe_batch_plan_set_launch(self._p, BATCH_LAUNCH[launch]))
 
     def autotune(self):
         """fe_batch_plan_autotune: keeps the faster tile size; returns (tile, {tile: ms})."""

@@ -1,17 +1,21 @@
 // Host side of the batched expansion: a plan lays the batch out in the workspace arena
 // (matrices sorted by decreasing layer count, then decreasing padded size), uploads the
 // per-matrix descriptors and the coefficient tables once and captures the whole launch sequence
-// (bounds, rescale, the grouped layers, reductions, and the entropy pass when requested) into one
-// hipGraph that each launch replays. With a model bank every matrix runs the model with the
+// (bounds, rescale, the layers, reductions, and the entropy pass when requested) into one
+// hipGraph that each launch replays. The layers of a pass run as one grouped launch per layer, or
+// as one queue launch over all layers (batch_queue.h). With a model bank every matrix runs the model with the
 // fewest layers whose region of validity (Eq. conditions) contains its (beta', mu').
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
+#include "batch_queue.h"
 #include "fe_host.h"
 
 using namespace fehost;
@@ -25,6 +29,8 @@ struct fe_batch_plan {
     fe_workspace* ws = nullptr;
     void* tables = nullptr; // device coefficient tables of both passes
     void* maps = nullptr;   // device XCD-affine tile maps of the layer launches
+    int launch = FE_BATCH_LAUNCH_QUEUE;    // one queue launch, or one grouped launch per layer
+    void* queues = nullptr; // device work queues and counters of the queue launch (both passes)
     // what a rebuild with another tile size needs (host copies)
     std::vector<fe_batch_item> items;
     std::vector<int> model;
@@ -36,6 +42,9 @@ struct fe_batch_plan {
 };
 
 namespace {
+
+// fe_debug_batch_queue_giveup: every wait of the queue launch expects a count never reached
+std::atomic<int> g_queue_giveup{0};
 
 int check_item(const fe_batch_item& it, int i) {
     if (!it.H) return fail(FE_ERR_ARG, "batch item " + std::to_string(i) + ": H is NULL");
@@ -123,19 +132,114 @@ std::vector<int32_t> xcd_map(const std::vector<fe::BatchMat>& mats, int k, int t
     return map;
 }
 
+// The queue (XCD) of each matrix of the sorted batch for the queue launch: dealt in batch order
+// to the queue with the least work so far, as in xcd_map.
+std::vector<int> deal_queues(const std::vector<fe::BatchMat>& mats, int tile, int nq) {
+    std::vector<double> load(nq, 0.0);
+    std::vector<int> q(mats.size());
+    for (size_t m = 0; m < mats.size(); ++m) {
+        const int64_t T = mats[m].np / tile, nt = T * (T + 1) / 2;
+        int x = 0;
+        for (int y = 1; y < nq; ++y)
+            if (load[y] < load[x]) x = y;
+        load[x] += (double)nt * (double)mats[m].np;
+        q[m] = x;
+    }
+    return q;
+}
+
+// Host image of one pass's queues: items {matrix, tile, layer, need} per queue, layer-major, and
+// the queue offsets. L[k]: layer count of model k in this pass.
+struct PassQueues {
+    std::vector<int32_t> items;   // 4 per item
+    std::vector<int32_t> qoff;    // nq + 1
+    int64_t longest = 0;
+};
+PassQueues make_queues(const std::vector<fe::BatchMat>& mats, const std::vector<int>& queue_of,
+                       const std::vector<int32_t>& L, int max_L, int tile, int nq) {
+    PassQueues pq;
+    pq.qoff.assign(nq + 1, 0);
+    for (int x = 0; x < nq; ++x) {
+        pq.qoff[x] = (int32_t)(pq.items.size() / 4);
+        for (int l = 0; l < max_L; ++l)
+            for (size_t m = 0; m < mats.size(); ++m) {
+                if (queue_of[m] != x || L[mats[m].model] <= l) continue;
+                const int64_t T = mats[m].np / tile, nt = T * (T + 1) / 2;
+                for (int64_t t = 0; t < nt; ++t) {
+                    pq.items.push_back((int32_t)m);
+                    pq.items.push_back((int32_t)t);
+                    pq.items.push_back(l);
+                    pq.items.push_back((int32_t)(l * nt));
+                }
+            }
+        const int64_t len = (int64_t)(pq.items.size() / 4) - pq.qoff[x];
+        pq.longest = std::max(pq.longest, len);
+    }
+    pq.qoff[nq] = (int32_t)(pq.items.size() / 4);
+    return pq;
+}
+
+// Queues of the queue launch on the current device (its XCD count), and whether the launch's
+// assumptions hold there (fe::batch_queue_probe, run once per device).
+int queue_support(int* nq_out, bool* ok) {
+    static std::mutex mu;
+    static std::vector<int> state;   // per device: 0 unknown, 1 available, 2 unavailable
+    static std::vector<int> nqs;
+    int dev = 0, nq = 0;
+    FE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)state.size() <= dev) {
+        state.resize(dev + 1, 0);
+        nqs.resize(dev + 1, 1);
+    }
+    if (state[dev] == 0) {
+        if (hipDeviceGetAttribute(&nq, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nq < 1)
+            nq = 1;
+        bool good = false;
+        FE_HIP(fe::batch_queue_probe(nq, &good));
+        state[dev] = good ? 1 : 2;
+        nqs[dev] = nq;
+    }
+    *nq_out = nqs[dev];
+    *ok = state[dev] == 1;
+    return FE_OK;
+}
+
+// Device view of one pass's queues for a launch.
+struct QueueLaunch {
+    fe::BatchQueue q{};
+    int64_t grid = 0;   // queues x longest queue
+};
+
 // One layer launch: its tile map on the device and the number of workgroups.
 struct LayerLaunch {
     const int32_t* map;
     int grid;
 };
 
-// Enqueues one expansion pass (density or entropy) of the whole batch on `s`; launches[l] is
-// layer l's launch (grid 0: no matrix has that many layers).
+// Enqueues one expansion pass (density or entropy) of the whole batch on `s`: with `queue`, all
+// layers in one queue launch; else launches[l] is layer l's grouped launch (grid 0: no matrix has
+// that many layers).
 int enqueue_pass(fe_workspace* ws, int count, int64_t max_np, const fe::BatchCoef& cf,
-                 const std::vector<LayerLaunch>& launches, double alpha, int entropy, int bf,
-                 int tile, int32_t* status, hipStream_t s) {
+                 const std::vector<LayerLaunch>& launches, const QueueLaunch* queue, double alpha,
+                 int entropy, int bf, int tile, int32_t* status, hipStream_t s) {
     if (!entropy) FE_HIP(fe::launch_batch_bounds(ws->bmats, count, ws->bparams, s));
     FE_HIP(fe::launch_batch_rescale(ws->bmats, count, max_np, ws->bparams, alpha, cf, bf, s));
+    if (queue) {
+        fe::BatchLayerArgs q{};
+        q.mats = ws->bmats;
+        q.count = count;
+        q.entropy = entropy;
+        q.cf = cf;
+        q.P = ws->bparams;
+        q.partials = ws->btparts;
+        FE_HIP(fe::launch_batch_queue_reset(queue->q, count, s));
+        FE_HIP(fe::launch_batch_queue(q, queue->q, queue->grid, bf, tile, s));
+        FE_HIP(fe::launch_batch_queue_check(ws->bmats, count, queue->q, cf, ws->bparams, tile, s));
+        FE_HIP(fe::launch_batch_reduce(ws->bmats, count, ws->btparts, ws->bparams, entropy, status,
+                                       tile, s));
+        return FE_OK;
+    }
     for (int l = 0; l < cf.max_L; ++l) {
         if (launches[l].grid == 0) break;
         fe::BatchLayerArgs q{};
@@ -237,10 +341,12 @@ void release_plan(fe_batch_plan* plan) {
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->tables) (void)hipFree(plan->tables);
     if (plan->maps) (void)hipFree(plan->maps);
+    if (plan->queues) (void)hipFree(plan->queues);
     plan->exec = nullptr;
     plan->graph = nullptr;
     plan->tables = nullptr;
     plan->maps = nullptr;
+    plan->queues = nullptr;
 }
 
 // Builds and captures `plan` for its stored inputs with layer tiles of `tile` (128 or 64): item i
@@ -365,6 +471,54 @@ int build_plan(fe_batch_plan* plan, int tile) {
     if (e == hipSuccess) e = up(eo + ce + le, te.d0.data(), te.d0.size() * 4);
     if (e == hipSuccess) e = up(eo + ce + le + de, te.shift0.data(), te.shift0.size() * 8);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch tables)");
+    // queue launch: per pass the items of every queue, then both passes' counters
+    QueueLaunch qd, qe;
+    int nq = 1;
+    bool queue_ok = false;
+    if (plan->launch == FE_BATCH_LAUNCH_QUEUE) {
+        int rcq = queue_support(&nq, &queue_ok);
+        if (rcq != FE_OK) return rcq;
+        if (!queue_ok) plan->launch = FE_BATCH_LAUNCH_LAYERS;   // the default falls back
+    }
+    const bool queued = plan->launch == FE_BATCH_LAUNCH_QUEUE;
+    if (queued) {
+        const std::vector<int> queue_of = deal_queues(mats, tile, nq);
+        const PassQueues pd = make_queues(mats, queue_of, td.L, td.max_L, tile, nq);
+        PassQueues pe;
+        if (!ent.empty()) pe = make_queues(mats, queue_of, te.L, te.max_L, tile, nq);
+        if (pd.longest * nq > 0x7fffffff || pe.longest * nq > 0x7fffffff)
+            return fail(FE_ERR_WORKSPACE, "batch has too many work items for one queue launch");
+        const size_t id = al(pd.items.size() * 4), ie = al(pe.items.size() * 4);
+        const size_t od = al(pd.qoff.size() * 4), oe = al(pe.qoff.size() * 4);
+        const size_t cn = al((size_t)fe::batch_queue_counters(nq, count) * 4);
+        e = hipMalloc(&plan->queues, id + ie + od + oe + cn + 256);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch queues)");
+        char* qb = static_cast<char*>(plan->queues);
+        auto upq = [&](size_t off, const std::vector<int32_t>& v) {
+            return v.empty() ? hipSuccess
+                             : hipMemcpy(qb + off, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+        };
+        e = upq(0, pd.items);
+        if (e == hipSuccess) e = upq(id, pe.items);
+        if (e == hipSuccess) e = upq(id + ie, pd.qoff);
+        if (e == hipSuccess) e = upq(id + ie + od, pe.qoff);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch queues)");
+        int32_t* counters = reinterpret_cast<int32_t*>(qb + id + ie + od + oe);
+        auto view = [&](QueueLaunch& v, size_t items_off, size_t qoff_off, int64_t longest) {
+            v.q.items = reinterpret_cast<const int4*>(qb + items_off);
+            v.q.qoff = reinterpret_cast<const int32_t*>(qb + qoff_off);
+            v.q.nq = nq;
+            v.q.ticket = counters;
+            v.q.done = counters + nq;
+            v.q.err = counters + nq + count;
+            const bool giveup = g_queue_giveup.load() != 0;
+            v.q.spin_limit = giveup ? 64 : (1 << 20);   // 1 << 20: ~1 s of polls
+            v.q.need_offset = giveup ? (1 << 30) : 0;
+            v.grid = longest * nq;
+        };
+        view(qd, 0, id + ie, pd.longest);
+        if (!ent.empty()) view(qe, id, id + ie + od, pe.longest);
+    }
     hipStream_t cs;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -372,9 +526,11 @@ int build_plan(fe_batch_plan* plan, int tile) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int bf = prec == FE_PREC_BF16X3 ? 2 : prec == FE_PREC_BF16X2 ? 1 : 0;
     if (e == hipSuccess) {
-        rc = enqueue_pass(ws, count, max_np, cfd, ll_d, 1.0, 0, bf, tile, status, cs);
+        rc = enqueue_pass(ws, count, max_np, cfd, ll_d, queued ? &qd : nullptr, 1.0, 0, bf,
+                          tile, status, cs);
         if (rc == FE_OK && !ent.empty())
-            rc = enqueue_pass(ws, count, max_np, cfe, ll_e, alpha, 1, bf, tile, status, cs);
+            rc = enqueue_pass(ws, count, max_np, cfe, ll_e, queued ? &qe : nullptr, alpha, 1, bf,
+                              tile, status, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         plan->graph = g;
@@ -526,6 +682,24 @@ int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile) {
     return build_plan(plan, tile);
 }
 
+int fe_batch_plan_set_launch(fe_batch_plan* plan, int32_t launch) {
+    if (!plan) return fail(FE_ERR_ARG, "invalid plan");
+    if (launch != FE_BATCH_LAUNCH_LAYERS && launch != FE_BATCH_LAUNCH_QUEUE)
+        return fail(FE_ERR_ARG, "launch must be FE_BATCH_LAUNCH_LAYERS or FE_BATCH_LAUNCH_QUEUE");
+    if (launch == FE_BATCH_LAUNCH_QUEUE) {
+        int nq = 1;
+        bool ok = false;
+        const int rc = queue_support(&nq, &ok);
+        if (rc != FE_OK) return rc;
+        if (!ok)
+            return fail(FE_ERR_ARG, "the queue launch is unavailable on this device (workgroups are "
+                                    "not dealt to its XCDs round-robin)");
+    }
+    FE_HIP(hipDeviceSynchronize());   // as in fe_batch_plan_retile
+    plan->launch = launch;
+    return build_plan(plan, plan->tile);
+}
+
 int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms) {
     if (!plan) return fail(FE_ERR_ARG, "invalid plan");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -564,6 +738,11 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
     }
     if (tile) *tile = best;
     return best == plan->tile ? FE_OK : build_plan(plan, best);
+}
+
+int fe_debug_batch_queue_giveup(int32_t enable) {
+    g_queue_giveup.store(enable ? 1 : 0);
+    return FE_OK;
 }
 
 int fe_batched_expand(const fe_batch_item* items, int32_t count, const fe_model* m,

@@ -5,6 +5,10 @@
 // rewritten (so X stays block diagonal) and is masked out of D and the traces.
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
+#include "batch_queue.h"
 #include "split_common.h"
 
 namespace fe {
@@ -175,48 +179,33 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
     }
 }
 
-// One layer for every upper tile of every matrix, then the same K loop and fused epilogue as the
-// single-matrix kernel. Workgroup g takes the (matrix, tile) of its slot in the plan's map, which
-// keeps all tiles of a matrix on one XCD (the hardware deals workgroup g to XCD g % 8), so the
-// matrix's operand panels are fetched into one L2 instead of eight; without a map it finds its
-// matrix by binary search over the tile prefix sums.
+// Layer `layer` of upper tile t of matrix `lo`: the same K loop and fused epilogue as the
+// single-matrix kernel. poisoned: the tile's inputs could not be waited for (queue launch);
+// its outputs are NaN.
+// mats, Ls, coef: q.mats, q.cf.L and q.cf.coef, which the queue kernel passes as separate
+// no-alias arguments: its atomics precede these loads, and only with the arguments' no-alias
+// guarantee does the compiler know them unwritten and load them into scalar registers (else the
+// descriptors take vector registers throughout the tile's code, which then spills).
 template <bool BF, class C>
-__global__ void __launch_bounds__(C::NT)
-__attribute__((amdgpu_waves_per_eu(4, 4)))
-k_batch_layer(BatchLayerArgs q) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int g = blockIdx.x;
-    int lo, t;
-    if (q.map) {
-        lo = q.map[2 * g];
-        t = q.map[2 * g + 1];
-        if (lo < 0) return;   // an empty slot; whole workgroup leaves
-    } else {
-        lo = 0;
-        int hi = q.count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (q.mats[mid].tile0 <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        t = g - q.mats[lo].tile0;
-    }
-    const BatchMat& m = q.mats[lo];
-    const int L = q.cf.L[m.model];
-    if (q.layer >= L) return;   // not launched for such matrices; whole workgroup leaves
-    const float* cf = q.cf.coef + ((size_t)m.model * q.cf.max_L + q.layer) * 8;
+__device__ __attribute__((always_inline)) inline void batch_tile(
+    const BatchLayerArgs& q, const BatchMat* __restrict__ mats, const int32_t* __restrict__ Ls,
+    const float* __restrict__ coef, int lo, int t, int layer, bool poisoned, unsigned char* smem) {
+    const BatchMat& m = mats[lo];
+    const int L = Ls[m.model];
+    const float* cf = coef + ((size_t)m.model * q.cf.max_L + layer) * 8;
     const int T = (int)(m.np / C::BM);
+    const int parity = layer & 1;
     int I, J;
     tile_coords(t, T, I, J);
     LayerArgs p;
     p.np = m.np;
     p.n = m.n;
-    p.hi_in = m.hi[q.parity];
-    p.lo_in = m.lo[q.parity];
-    p.hi_out = m.hi[q.parity ^ 1];
-    p.lo_out = m.lo[q.parity ^ 1];
-    p.mid_in = m.mid[q.parity];
-    p.mid_out = m.mid[q.parity ^ 1];
+    p.hi_in = m.hi[parity];
+    p.lo_in = m.lo[parity];
+    p.hi_out = m.hi[parity ^ 1];
+    p.lo_out = m.lo[parity ^ 1];
+    p.mid_in = m.mid[parity];
+    p.mid_out = m.mid[parity ^ 1];
     p.X = m.X;
     p.A = m.A;
     p.a = cf[0];
@@ -225,7 +214,7 @@ k_batch_layer(BatchLayerArgs q) {
     p.d_old = cf[3];
     p.d_new = cf[4];
     p.affine = cf[5] != 0.0f;
-    p.last = q.layer == L - 1;
+    p.last = layer == L - 1;
     p.entropy = q.entropy;
     p.D = m.D;
     p.ldd = m.ldd;
@@ -248,7 +237,123 @@ k_batch_layer(BatchLayerArgs q) {
     else
         kloop<BF, C>(p.hi_in, p.lo_in, p.np, (int64_t)I * C::BM, (int64_t)J * C::BM, 0, kend, acc,
                      reinterpret_cast<uint16_t*>(smem));
-    epilogue<BF, C, C::BM == 128 ? kBatchEpiGroups : 8>(p, acc, reinterpret_cast<float*>(smem), I, J, t);
+    epilogue<BF, C, C::BM == 128 ? kBatchEpiGroups : 8>(p, acc, reinterpret_cast<float*>(smem), I, J,
+                                                        t, nullptr, 0, 0, poisoned);
+}
+
+// One layer for every upper tile of every matrix. Workgroup g takes the (matrix, tile) of its slot
+// in the plan's map, which keeps all tiles of a matrix on one XCD (the hardware deals workgroup g
+// to XCD g % 8), so the matrix's operand panels are fetched into one L2 instead of eight; without
+// a map it finds its matrix by binary search over the tile prefix sums.
+template <bool BF, class C>
+__global__ void __launch_bounds__(C::NT)
+__attribute__((amdgpu_waves_per_eu(4, 4)))
+k_batch_layer(BatchLayerArgs q) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int g = blockIdx.x;
+    int lo, t;
+    if (q.map) {
+        lo = q.map[2 * g];
+        t = q.map[2 * g + 1];
+        if (lo < 0) return;   // an empty slot; whole workgroup leaves
+    } else {
+        lo = 0;
+        int hi = q.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.mats[mid].tile0 <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        t = g - q.mats[lo].tile0;
+    }
+    if (q.layer >= q.cf.L[q.mats[lo].model]) return;   // not launched for such matrices
+    batch_tile<BF, C>(q, q.mats, q.cf.L, q.cf.coef, lo, t, q.layer, false, smem);
+}
+
+// Every layer of every matrix of a pass in one launch (the queue protocol is described with
+// BatchQueue): each workgroup takes the next ticket of its XCD's queue, waits until the item's
+// matrix has completed its previous layer, computes the item, and once every wave's stores of it
+// have completed counts it done. The wait is bounded: one that gives up marks the matrix and
+// raises the abort flag, after which no wait blocks; such an item is computed with NaN outputs.
+// Workgroups beyond their queue's length leave at once.
+template <bool BF, class C>
+__global__ void __launch_bounds__(C::NT)
+__attribute__((amdgpu_waves_per_eu(4, 4)))
+k_batch_queue(BatchLayerArgs q, BatchQueue Q, const BatchMat* __restrict__ mats,
+              const int32_t* __restrict__ Ls, const float* __restrict__ coef) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int4 s_item;
+    __shared__ int s_gave_up;
+    if (threadIdx.x == 0) {
+        int x;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+        int4 it = make_int4(-1, 0, 0, 0);   // none: no queue for this XCD (the completion check
+                                            // reports the matrices), or the queue is exhausted
+        if (x < Q.nq) {
+            const int q0 = Q.qoff[x], total = Q.qoff[x + 1] - q0;
+            const int k = __hip_atomic_fetch_add(Q.ticket + x, 1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (k < total) it = Q.items[q0 + k];
+        }
+        int gave_up = 0;
+        if (it.x >= 0) {
+            int32_t* const abort_flag = Q.err + q.count;
+            int spins = 0;
+            const int need = it.w + Q.need_offset;
+            while (__hip_atomic_load(Q.done + it.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   need) {
+                if (++spins > Q.spin_limit ||
+                    __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(Q.err + it.x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    gave_up = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        s_item = it;
+        s_gave_up = gave_up;
+    }
+    // Lines of the matrix that this CU's L1 holds from before its producers' stores are stale:
+    // wave 0 invalidates the L1 and waits for that before the barrier, after which every wave
+    // loads. The invalidate takes agent scope: the workgroup-scope one leaves the L1 alone when a
+    // workgroup's waves share one CU (measured: it does not stop stale reads here).
+    if (threadIdx.x < 64) asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const int mat = __builtin_amdgcn_readfirstlane(s_item.x);
+    if (mat < 0) return;   // nothing to do; whole workgroup leaves
+    const int t = __builtin_amdgcn_readfirstlane(s_item.y);
+    const int layer = __builtin_amdgcn_readfirstlane(s_item.z);
+    const bool gave_up = __builtin_amdgcn_readfirstlane(s_gave_up) != 0;
+    batch_tile<BF, C>(q, mats, Ls, coef, mat, t, layer, gave_up, smem);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores of the item have completed
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(Q.done + mat, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// XCD of workgroup b (one wave each), for the check that the queue launch's assumptions hold.
+__global__ void __launch_bounds__(64) k_xcc_probe(int32_t* out, int n) {
+    if (threadIdx.x != 0 || (int)blockIdx.x >= n) return;
+    int x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+    out[blockIdx.x] = x;
+}
+
+__global__ void __launch_bounds__(256) k_batch_queue_reset(int32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_queue_check(const BatchMat* mats, int count, BatchQueue Q, BatchCoef cf, Params* P,
+                    int tile) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= count) return;
+    const BatchMat& m = mats[b];
+    const int64_t T = m.np / tile;
+    const int64_t want = (int64_t)cf.L[m.model] * (T * (T + 1) / 2);
+    if ((Q.done[b] != want || Q.err[b] != 0) && P[b].status >= 0) P[b].status = FE_ERR_HIP;
 }
 
 // Per-matrix fixed-order reduction of the tile traces into Tr, sum of squares, and S (entropy).
@@ -326,6 +431,65 @@ hipError_t launch_batch_layer(const BatchLayerArgs& q, int grid, int bf16, int t
     if (tile != 128) return hipErrorInvalidValue;
     return bf16 ? launch_layer_t<true, CfgB>(q, grid, s)
                 : launch_layer_t<false, CfgB>(q, grid, s);
+}
+
+template <bool BF, class C>
+hipError_t queue_t(const BatchLayerArgs& q, const BatchQueue& Q, int64_t grid, hipStream_t s) {
+    auto kern = k_batch_queue<BF, C>;
+    static bool done = false;
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)C::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        done = true;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::NT), C::LDS_BYTES, s, q, Q, q.mats,
+                       q.cf.L, q.cf.coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_queue_reset(const BatchQueue& Q, int count, hipStream_t s) {
+    const int64_t n = batch_queue_counters(Q.nq, count);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 256);
+    hipLaunchKernelGGL(k_batch_queue_reset, dim3(blocks), dim3(256), 0, s, Q.ticket, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_queue(const BatchLayerArgs& q, const BatchQueue& Q, int64_t grid, int bf16,
+                              int tile, hipStream_t s) {
+    if (grid < 1 || grid > 0x7fffffff) return hipErrorInvalidValue;
+    if (bf16 == 2) return tile == 128 ? queue_t<true, CfgB3>(q, Q, grid, s) : hipErrorInvalidValue;
+    if (tile == 64)
+        return bf16 ? queue_t<true, CfgB64>(q, Q, grid, s) : queue_t<false, CfgB64>(q, Q, grid, s);
+    if (tile != 128) return hipErrorInvalidValue;
+    return bf16 ? queue_t<true, CfgB>(q, Q, grid, s) : queue_t<false, CfgB>(q, Q, grid, s);
+}
+
+hipError_t batch_queue_probe(int nq, bool* ok) {
+    *ok = false;
+    if (nq < 1 || nq > 16) return hipSuccess;
+    const int n = 64 * nq;
+    int32_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, n * sizeof(int32_t));
+    if (e != hipSuccess) return e;
+    std::vector<int32_t> h(n, -1);
+    hipLaunchKernelGGL(k_xcc_probe, dim3(n), dim3(64), 0, nullptr, d, n);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return e;
+    bool good = true;
+    for (int b = 0; b < n; ++b) good = good && h[b] == b % nq;
+    *ok = good;
+    return hipSuccess;
+}
+
+hipError_t launch_batch_queue_check(const BatchMat* mats, int count, const BatchQueue& Q,
+                                    BatchCoef cf, Params* P, int tile, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_queue_check, dim3((count + 255) / 256), dim3(256), 0, s, mats, count,
+                       Q, cf, P, tile);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_reduce(const BatchMat* mats, int count, const TracePartial* partials,

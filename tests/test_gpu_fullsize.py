@@ -95,6 +95,18 @@ def test_batch1024_sampled_against_oracle(api):
         within(f"batch1024 item {b} |dD|_F/N", fro, MEASURED_1024[b][0], cap=1e-5)
         within(f"batch1024 item {b} |dTrD|", dtr, MEASURED_1024[b][1])
         assert np.array_equal(Dg, Dg.T)
+    # the plan's default launch (every layer in one queue launch, as the benchmark times it)
+    # against one grouped launch per layer: bitwise equal over the whole batch
+    print("case batch1024 fp16x2 queue launch vs per-layer launches", flush=True)
+    Dq = [d.clone() for d in plan.D]
+    trq = plan.tr.clone()
+    plan.set_launch("layers")
+    plan.launch()
+    torch.cuda.synchronize()
+    assert int(np.count_nonzero(plan.status.cpu().numpy())) == 0
+    assert all(torch.equal(plan.D[b], Dq[b]) for b in range(1024))
+    assert torch.equal(plan.tr, trq)
+    del Dq
     # the same batch over the benchmark's model bank (each matrix runs its selected model)
     import bench
     bank = [models.load(x) for x in bench.BANK]
