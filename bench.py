@@ -474,9 +474,14 @@ def bench_batch(args, torch, api, models, workloads, dev):
     plan = api.BatchPlan(mats, m, prec=prec)
     tile, tile_ms = plan.autotune()
     other = "queue" if args.batch_launch == "layers" else "layers"
-    plan.set_launch(other)
-    ms_other = timed(plan.launch, args.steps, args.warmup, torch)
-    plan.set_launch(args.batch_launch)
+    try:
+        plan.set_launch(other)
+        ms_other = timed(plan.launch, args.steps, args.warmup, torch)
+        plan.set_launch(args.batch_launch)
+    except api.FeError as e:   # the queue launch is unavailable on this device (probe failed)
+        print(f"batch launch form: {e}", file=sys.stderr, flush=True)
+        ms_other = None
+        plan.set_launch("layers")
     ms = timed(plan.launch, args.steps, args.warmup, torch)
     status = plan.status.cpu().numpy()
     ns = np.array([it["n"] for it in items], dtype=np.float64)
@@ -492,16 +497,21 @@ def bench_batch(args, torch, api, models, workloads, dev):
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "status_nonzero": int(np.count_nonzero(status)),
            "tile_autotune": {"tile": tile, "ms_per_step": {str(k): v for k, v in tile_ms.items()}},
-           "launch": {"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms, other: ms_other}}}
+           "launch": ({"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms, other: ms_other}}
+                      if ms_other is not None else {"form": "layers", "ms_per_step": {"layers": ms}})}
     # the same batch over the model bank: each matrix runs the fewest layers valid for it
     bank_names = BANK
     bank = [models.load(x) for x in bank_names]
     plan.close()
     bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)
     tile_b, tile_ms_b = bplan.autotune()
-    bplan.set_launch(other)
-    ms_b_other = timed(bplan.launch, args.steps, args.warmup, torch)
-    bplan.set_launch(args.batch_launch)
+    ms_b_other = None
+    if ms_other is not None:
+        bplan.set_launch(other)
+        ms_b_other = timed(bplan.launch, args.steps, args.warmup, torch)
+        bplan.set_launch(args.batch_launch)
+    else:
+        bplan.set_launch("layers")
     ms_b = timed(bplan.launch, args.steps, args.warmup, torch)
     Ls = np.array([bank[k].L for k in bplan.chosen], dtype=np.float64)
     out["model_bank"] = {
@@ -511,7 +521,8 @@ def bench_batch(args, torch, api, models, workloads, dev):
         "tflops_algorithmic": float(np.sum(Ls * 2.0 * ns ** 3)) / (ms_b * 1e-3) / 1e12,
         "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy())),
         "tile_autotune": {"tile": tile_b, "ms_per_step": {str(k): v for k, v in tile_ms_b.items()}},
-        "launch": {"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms_b, other: ms_b_other}}}
+        "launch": ({"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms_b, other: ms_b_other}}
+                   if ms_b_other is not None else {"form": "layers", "ms_per_step": {"layers": ms_b}})}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         order = np.argsort(ns)
