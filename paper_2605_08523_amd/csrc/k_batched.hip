@@ -327,7 +327,9 @@ k_batch_queue(BatchLayerArgs q, BatchQueue Q, const BatchMat* __restrict__ mats,
     const int layer = __builtin_amdgcn_readfirstlane(s_item.z);
     const bool gave_up = __builtin_amdgcn_readfirstlane(s_gave_up) != 0;
     batch_tile<BF, C>(q, mats, Ls, coef, mat, t, layer, gave_up, smem);
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores of the item have completed
+    // This wave's stores of the item have completed (in the XCD's L2). The memory clobber keeps
+    // the compiler from sinking any of them below the wait.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0)
         __hip_atomic_fetch_add(Q.done + mat, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
