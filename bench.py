@@ -52,9 +52,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--prec", default="fp16x2", choices=["fp16x2", "bf16x2", "bf16x3"],
                    help="bf16x3 (three-part BF16 split, six products): batch1024 only")
-    p.add_argument("--batch-launch", default="queue", choices=["queue", "layers"],
-                   help="batch1024: every layer in one queue launch (default), or one grouped "
-                        "launch per layer")
+    p.add_argument("--batch-launch", default="auto", choices=["auto", "queue", "layers"],
+                   help="batch1024: the plan tuner's choice (default), every layer in one queue "
+                        "launch, or one grouped launch per layer")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-gpu-baselines", action="store_true")
     p.add_argument("--profile", action="store_true", help="only the timed steps (for rocprofv3)")
@@ -456,11 +456,26 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def launch_form(api, plan, want):
+    """The launch form to time: the plan tuner's choice ("auto"), else the one asked for (the
+    queue launch falls back to the per-layer launches where the device does not allow it).
+    Returns (form, tuner's choice)."""
+    tuned = plan.launch_form
+    if want == "auto" or want == tuned:
+        return tuned, tuned
+    try:
+        plan.set_launch(want)
+        return want, tuned
+    except api.FeError as e:
+        print(f"batch launch form {want}: {e}", file=sys.stderr, flush=True)
+        return tuned, tuned
+
+
 def bench_batch(args, torch, api, models, workloads, dev):
     """1024 Hamiltonians, N_b ~ U{64..768}, one captured plan (a hipGraph: bounds, rescale, every
-    layer of every matrix in one queue launch (--batch-launch layers: one grouped launch per layer,
-    the other form timed beside it), traces; its layer tile, 128 x 128 or 64 x 64, chosen by the
-    plan's autotuner), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
+    layer of every matrix in one queue launch, or one grouped launch per layer, traces; its layer
+    tile, 128 x 128 or 64 x 64, and its launch form chosen by the plan's autotuner, the other form
+    timed beside it), the 40-layer (beta0 = 1e4, mu0 = 1/3) model, FP16x2 by default (BF16x2 misses the
     1e-5 bar on this batch: beta' reaches ~3700; --prec bf16x3, the three-part BF16 split, meets
     it). Sampled items are checked against the CPU oracle (eigendecomposition) in the
     cpu_baseline leg."""
@@ -473,15 +488,15 @@ def bench_batch(args, torch, api, models, workloads, dev):
     prec = args.prec
     plan = api.BatchPlan(mats, m, prec=prec)
     tile, tile_ms = plan.autotune()
-    other = "queue" if args.batch_launch == "layers" else "layers"
-    try:
+    form, tuned_form = launch_form(api, plan, args.batch_launch)
+    other = "queue" if form == "layers" else "layers"
+    ms_other = None
+    try:   # the other form, timed for comparison (the queue launch may be unavailable)
         plan.set_launch(other)
         ms_other = timed(plan.launch, args.steps, args.warmup, torch)
-        plan.set_launch(args.batch_launch)
-    except api.FeError as e:   # the queue launch is unavailable on this device (probe failed)
-        print(f"batch launch form: {e}", file=sys.stderr, flush=True)
-        ms_other = None
-        plan.set_launch("layers")
+    except api.FeError as e:
+        print(f"batch launch form {other}: {e}", file=sys.stderr, flush=True)
+    plan.set_launch(form)
     ms = timed(plan.launch, args.steps, args.warmup, torch)
     status = plan.status.cpu().numpy()
     ns = np.array([it["n"] for it in items], dtype=np.float64)
@@ -497,21 +512,23 @@ def bench_batch(args, torch, api, models, workloads, dev):
            "tflops_algorithmic": flop / (ms * 1e-3) / 1e12,
            "status_nonzero": int(np.count_nonzero(status)),
            "tile_autotune": {"tile": tile, "ms_per_step": {str(k): v for k, v in tile_ms.items()}},
-           "launch": ({"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms, other: ms_other}}
-                      if ms_other is not None else {"form": "layers", "ms_per_step": {"layers": ms}})}
+           "launch": {"form": form, "tuned": tuned_form,
+                      "ms_per_step": {form: ms, other: ms_other}}}
     # the same batch over the model bank: each matrix runs the fewest layers valid for it
     bank_names = BANK
     bank = [models.load(x) for x in bank_names]
     plan.close()
     bplan = api.BatchPlan(mats, bank, prec=prec, ws=plan.ws)
     tile_b, tile_ms_b = bplan.autotune()
+    form_b, tuned_b = launch_form(api, bplan, args.batch_launch)
+    other_b = "queue" if form_b == "layers" else "layers"
     ms_b_other = None
-    if ms_other is not None:
-        bplan.set_launch(other)
+    try:
+        bplan.set_launch(other_b)
         ms_b_other = timed(bplan.launch, args.steps, args.warmup, torch)
-        bplan.set_launch(args.batch_launch)
-    else:
-        bplan.set_launch("layers")
+    except api.FeError as e:
+        print(f"batch launch form {other_b}: {e}", file=sys.stderr, flush=True)
+    bplan.set_launch(form_b)
     ms_b = timed(bplan.launch, args.steps, args.warmup, torch)
     Ls = np.array([bank[k].L for k in bplan.chosen], dtype=np.float64)
     out["model_bank"] = {
@@ -521,8 +538,8 @@ def bench_batch(args, torch, api, models, workloads, dev):
         "tflops_algorithmic": float(np.sum(Ls * 2.0 * ns ** 3)) / (ms_b * 1e-3) / 1e12,
         "status_nonzero": int(np.count_nonzero(bplan.status.cpu().numpy())),
         "tile_autotune": {"tile": tile_b, "ms_per_step": {str(k): v for k, v in tile_ms_b.items()}},
-        "launch": ({"form": args.batch_launch, "ms_per_step": {args.batch_launch: ms_b, other: ms_b_other}}
-                   if ms_b_other is not None else {"form": "layers", "ms_per_step": {"layers": ms_b}})}
+        "launch": {"form": form_b, "tuned": tuned_b,
+                   "ms_per_step": {form_b: ms_b, other_b: ms_b_other}}}
     if not args.no_cpu_baseline:
         from oracle import fermi as F
         order = np.argsort(ns)

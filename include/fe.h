@@ -267,12 +267,17 @@ int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
  * FE_BATCH_LAUNCH_QUEUE where the device probe failed (the plan is then left as it was). */
 int fe_batch_plan_set_launch(fe_batch_plan* plan, int32_t launch);
 
-/* Autotunes the plan's tile size: builds it with each tile size, times three replays of each on
- * `stream` (after a warm-up), keeps the faster. tile (host, may be NULL) receives the choice, ms
- * (host, 2 entries, may be NULL) the ms per replay for tiles 128 and 64. Runs the batch 8 times;
- * waits for the device first and synchronizes. FE_PREC_BF16X3 plans have the 128 x 128 tile only
- * (ms[1] = NaN; fe_batch_plan_retile to 64 returns FE_ERR_ARG). */
+/* Autotunes the plan's tile size and launch form: builds it with each tile size (128 and 64;
+ * FE_PREC_BF16X3 plans have the 128 x 128 tile only) under each launch form (the queue launch
+ * where the device allows it, and the per-layer launches), times three replays of each on
+ * `stream` (after a warm-up) and keeps the fastest pair. tile (host, may be NULL) receives the
+ * chosen tile size, ms (host, 2 entries, may be NULL) the ms per replay for tiles 128 and 64 (the
+ * faster launch form of each; NaN for a tile not tried). Waits for the device first and
+ * synchronizes; on failure the plan is rebuilt in the default form. fe_batch_plan_get reports
+ * the choice. */
 int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, double* ms);
+/* The plan's current layer tile size and launch form (host outputs, each may be NULL). */
+int fe_batch_plan_get(const fe_batch_plan* plan, int32_t* tile, int32_t* launch);
 int fe_batch_plan_destroy(fe_batch_plan* plan);
 
 /* One-shot batch: create a plan, launch it on `stream`, wait for the stream, destroy the plan. */

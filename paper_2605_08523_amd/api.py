@@ -87,6 +87,7 @@ SIGNATURES = {
     "fe_layer_count": (_D, [_D]),
     "fe_batch_plan_retile": (_I32, [_P, _I32]),
     "fe_batch_plan_set_launch": (_I32, [_P, _I32]),
+    "fe_batch_plan_get": (_I32, [_P, C.POINTER(_I32), C.POINTER(_I32)]),
     "fe_batch_plan_autotune": (_I32, [_P, _P, C.POINTER(_I32), C.POINTER(_D)]),
     "fe_autotune": (_I32, [C.POINTER(_I64), _I32, _I32, C.POINTER(_I32), C.POINTER(_D), _P, _P]),
     "fe_autotune_input": (_I32, [_P, _I64, _I64, _D, _D, C.POINTER(fe_model), _I32, C.POINTER(_I32),
@@ -591,8 +592,23 @@ class BatchPlan:
         layer of every matrix in one launch)."""
         _check(lib().fe_batch_plan_set_launch(self._p, BATCH_LAUNCH[launch]))
 
+    @property
+    def launch_form(self) -> str:
+        """fe_batch_plan_get: "queue" or "layers"."""
+        launch = C.c_int32()
+        _check(lib().fe_batch_plan_get(self._p, None, C.byref(launch)))
+        return {v: k for k, v in BATCH_LAUNCH.items()}[launch.value]
+
+    @property
+    def tile(self) -> int:
+        """fe_batch_plan_get: the layer tile size (128 or 64)."""
+        tile = C.c_int32()
+        _check(lib().fe_batch_plan_get(self._p, C.byref(tile), None))
+        return tile.value
+
     def autotune(self):
-        """fe_batch_plan_autotune: keeps the faster tile size; returns (tile, {tile: ms})."""
+        """fe_batch_plan_autotune: keeps the fastest tile size and launch form; returns
+        (tile, {tile: ms of its faster launch form}); `launch_form` holds the chosen form."""
         tile = C.c_int32()
         ms = (C.c_double * 2)()
         _check(lib().fe_batch_plan_autotune(self._p, _stream_ptr(), C.byref(tile), ms))

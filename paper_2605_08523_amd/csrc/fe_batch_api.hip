@@ -704,19 +704,31 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
     if (!plan) return fail(FE_ERR_ARG, "invalid plan");
     hipStream_t s = static_cast<hipStream_t>(stream);
     FE_HIP(hipDeviceSynchronize());   // as in fe_batch_plan_retile
-    const int cand[2] = {128, 64};
-    const int ncand = plan->prec == FE_PREC_BF16X3 ? 1 : 2;   // three parts: 128 x 128 only
-    double t_ms[2] = {0.0, 0.0};
+    int nq = 1;
+    bool queue_ok = false;
+    {
+        const int rc = queue_support(&nq, &queue_ok);
+        if (rc != FE_OK) return rc;
+    }
+    // candidates: tile x launch form (the three-part split has the 128 x 128 tile only)
+    struct Cand {
+        int tile, launch;
+        double ms;
+    };
+    std::vector<Cand> cands;
+    for (int t : {128, 64}) {
+        if (t == 64 && plan->prec == FE_PREC_BF16X3) continue;
+        if (queue_ok) cands.push_back({t, FE_BATCH_LAUNCH_QUEUE, NAN});
+        cands.push_back({t, FE_BATCH_LAUNCH_LAYERS, NAN});
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     FE_HIP(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
     int rc = FE_OK;
-    for (int c = 0; c < ncand && rc == FE_OK && e == hipSuccess; ++c) {
-        rc = build_plan(plan, cand[c]);
-        if (rc != FE_OK) {
-            if (cand[c] != 128) (void)build_plan(plan, 128);   // leave the plan usable
-            break;
-        }
+    for (size_t c = 0; c < cands.size() && rc == FE_OK && e == hipSuccess; ++c) {
+        plan->launch = cands[c].launch;
+        rc = build_plan(plan, cands[c].tile);
+        if (rc != FE_OK) break;
         for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {   // one warm-up, three timed
             if (rep == 1) e = hipEventRecord(e0, s);
             if (e == hipSuccess) e = hipGraphLaunch(plan->exec, s);
@@ -725,19 +737,37 @@ int fe_batch_plan_autotune(fe_batch_plan* plan, void* stream, int32_t* tile, dou
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-        t_ms[c] = t / 3.0;
+        cands[c].ms = t / 3.0;
     }
     (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "batch autotune");
-    if (rc != FE_OK) return rc;
-    const int best = ncand > 1 && t_ms[1] < t_ms[0] ? 64 : 128;
-    if (ms) {
-        ms[0] = t_ms[0];
-        ms[1] = ncand > 1 ? t_ms[1] : NAN;
+    if (e != hipSuccess || rc != FE_OK) {
+        // leave the plan usable: the default form at 128 x 128
+        plan->launch = queue_ok ? FE_BATCH_LAUNCH_QUEUE : FE_BATCH_LAUNCH_LAYERS;
+        (void)build_plan(plan, 128);
+        return e != hipSuccess ? hip_fail(e, "batch autotune") : rc;
     }
-    if (tile) *tile = best;
-    return best == plan->tile ? FE_OK : build_plan(plan, best);
+    size_t best = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+        if (cands[c].ms < cands[best].ms) best = c;
+    if (ms) {
+        ms[0] = ms[1] = NAN;
+        for (const Cand& c : cands) {
+            double& m = ms[c.tile == 128 ? 0 : 1];
+            if (!(m <= c.ms)) m = c.ms;   // the faster launch form of each tile size
+        }
+    }
+    if (tile) *tile = cands[best].tile;
+    if (plan->tile == cands[best].tile && plan->launch == cands[best].launch) return FE_OK;
+    plan->launch = cands[best].launch;
+    return build_plan(plan, cands[best].tile);
+}
+
+int fe_batch_plan_get(const fe_batch_plan* plan, int32_t* tile, int32_t* launch) {
+    if (!plan) return fail(FE_ERR_ARG, "invalid plan");
+    if (tile) *tile = plan->tile;
+    if (launch) *launch = plan->launch;
+    return FE_OK;
 }
 
 int fe_debug_batch_queue_giveup(int32_t enable) {

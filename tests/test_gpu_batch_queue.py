@@ -141,3 +141,28 @@ def test_queue_launch_tiny_matrices_every_replay(api, paper_model):
         torch.cuda.synchronize()
         assert_same(plan, ref, f"tiny matrices, queue replay {rep}")
     plan.close()
+
+
+def test_autotune_chooses_tile_and_launch_form(api, paper_model):
+    """fe_batch_plan_autotune times both tile sizes under both launch forms and keeps the fastest
+    pair (fe_batch_plan_get reports it); the tuned plan's results equal the default plan's at the
+    same tile (both launch forms are bitwise equal, the tiles agree to FP32 rounding)."""
+    mats = uneven_batch(10, 4500, n_hi=300)
+    plan = api.BatchPlan(mats, paper_model, prec="fp16x2")
+    assert plan.launch_form == "queue" and plan.tile == 128
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = snapshot(plan)
+    print("case batch10 autotune (tile x launch form)", flush=True)
+    tile, ms = plan.autotune()
+    print(f"[batch autotune] tile {tile} launch {plan.launch_form} {ms}", flush=True)
+    assert plan.tile == tile and plan.launch_form in ("queue", "layers")
+    assert set(ms) == {64, 128} and ms[tile] == min(ms.values())
+    plan.launch()
+    torch.cuda.synchronize()
+    if tile == 128:
+        assert_same(plan, ref, "tuned plan")
+    else:
+        for b in range(plan.count):
+            assert float((plan.D[b] - ref[0][b]).abs().max()) < 1e-4
+    plan.close()
