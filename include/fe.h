@@ -507,6 +507,14 @@ int fe_streamk_segments(int64_t np, int32_t schedule, int32_t grid, int32_t w, i
  * give-up are NaN, the traces NaN, and the rescale info status FE_ERR_HIP. */
 int fe_debug_streamk_giveup(int32_t enable);
 
+/* Host-side view of the queue launch's work tables (no device work; for tests of the layout the
+ * kernel relies on): matrices of padded sizes np[i] (multiples of tile) running L[i] layers, in
+ * that (batch) order, dealt to nq queues as a plan deals them. items: host int32[4 * cap] or
+ * NULL, receives {matrix, tile, layer, need} per item, queue after queue, each queue in ticket
+ * order; qoff: host int32[nq + 1], queue x = items [qoff[x], qoff[x + 1]); nitems: the total. */
+int fe_batch_queue_layout(int32_t count, const int64_t* np, const int32_t* L, int32_t tile,
+                          int32_t nq, int32_t* items, int64_t cap, int32_t* qoff, int64_t* nitems);
+
 /* Test hook for failure handling (process-wide), the same for the batch queue launch
  * (FE_BATCH_LAUNCH_QUEUE): batch plans built while it is enabled wait, for every work item, for a
  * completion count that no matrix reaches; the first wait gives up after a short bounded spin and

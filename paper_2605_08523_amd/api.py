@@ -108,6 +108,8 @@ SIGNATURES = {
                                    C.POINTER(_I32)]),
     "fe_debug_streamk_giveup": (_I32, [_I32]),
     "fe_debug_batch_queue_giveup": (_I32, [_I32]),
+    "fe_batch_queue_layout": (_I32, [_I32, C.POINTER(_I64), C.POINTER(_I32), _I32, _I32,
+                                     C.POINTER(_I32), _I64, C.POINTER(_I32), C.POINTER(_I64)]),
     "fe_debug_layer_events": (_I32, [_I32]),
     "fe_debug_layer_events_read": (_I32, [C.POINTER(_D), _I32, C.POINTER(_I32)]),
     "fe_last_error": (C.c_char_p, []),
@@ -484,6 +486,24 @@ def layer_events_read():
 def debug_streamk_giveup(enable: bool) -> None:
     """fe_debug_streamk_giveup: make every stream-K wait give up (failure-handling tests)."""
     _check(lib().fe_debug_streamk_giveup(1 if enable else 0))
+
+
+def batch_queue_layout(np_list, L_list, tile: int, nq: int):
+    """fe_batch_queue_layout: the queue launch's work items for matrices of padded sizes np_list
+    running L_list layers (batch order). Returns (items int32 [n, 4]: matrix, tile, layer, need;
+    qoff int32 [nq + 1])."""
+    count = len(np_list)
+    npa = (C.c_int64 * count)(*[int(v) for v in np_list])
+    La = (C.c_int32 * count)(*[int(v) for v in L_list])
+    qoff = np.zeros(nq + 1, dtype=np.int32)
+    n = C.c_int64()
+    _check(lib().fe_batch_queue_layout(count, npa, La, int(tile), int(nq), None, 0,
+                                       qoff.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+    items = np.zeros((max(n.value, 1), 4), dtype=np.int32)
+    _check(lib().fe_batch_queue_layout(count, npa, La, int(tile), int(nq),
+                                       items.ctypes.data_as(C.POINTER(C.c_int32)), n.value,
+                                       qoff.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+    return items[:n.value], qoff
 
 
 def debug_batch_queue_giveup(enable: bool) -> None:

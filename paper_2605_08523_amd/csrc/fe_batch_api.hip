@@ -770,6 +770,33 @@ int fe_batch_plan_get(const fe_batch_plan* plan, int32_t* tile, int32_t* launch)
     return FE_OK;
 }
 
+int fe_batch_queue_layout(int32_t count, const int64_t* np, const int32_t* L, int32_t tile,
+                          int32_t nq, int32_t* items, int64_t cap, int32_t* qoff, int64_t* nitems) {
+    if (count < 1 || !np || !L || !qoff || !nitems) return fail(FE_ERR_ARG, "bad arguments");
+    if (tile != 64 && tile != 128) return fail(FE_ERR_ARG, "tile must be 64 or 128");
+    if (nq < 1 || nq > 16) return fail(FE_ERR_ARG, "nq must be 1 .. 16");
+    std::vector<fe::BatchMat> mats(count);
+    std::vector<int32_t> Lm(count);
+    int max_L = 0;
+    for (int i = 0; i < count; ++i) {
+        if (np[i] < tile || np[i] % tile != 0 || L[i] < 1)
+            return fail(FE_ERR_ARG, "np must be a positive multiple of the tile, L >= 1");
+        memset(&mats[i], 0, sizeof(mats[i]));
+        mats[i].np = np[i];
+        mats[i].model = i;   // one "model" per matrix: its layer count
+        Lm[i] = L[i];
+        max_L = std::max(max_L, (int)L[i]);
+    }
+    const PassQueues pq = make_queues(mats, deal_queues(mats, tile, nq), Lm, max_L, tile, nq);
+    *nitems = (int64_t)pq.items.size() / 4;
+    for (int x = 0; x <= nq; ++x) qoff[x] = pq.qoff[x];
+    if (items) {
+        if (cap < *nitems) return fail(FE_ERR_ARG, "items too small");
+        memcpy(items, pq.items.data(), pq.items.size() * sizeof(int32_t));
+    }
+    return FE_OK;
+}
+
 int fe_debug_batch_queue_giveup(int32_t enable) {
     g_queue_giveup.store(enable ? 1 : 0);
     return FE_OK;
