@@ -135,7 +135,9 @@ k_batch_bounds(const BatchMat* mats, int count, Params* P) {
     P[b] = p;
 }
 
-// Rescale and split of every matrix: blockIdx.y selects the matrix, blockIdx.x a chunk.
+// Rescale and split of every matrix: blockIdx.y selects the matrix, blockIdx.x a chunk; four
+// consecutive columns per thread (16-byte stores; np is a multiple of the tile), the same
+// per-element arithmetic as the single-matrix rescale.
 template <bool BF>
 __global__ void __launch_bounds__(256)
 k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, BatchCoef cf,
@@ -147,34 +149,47 @@ k_batch_rescale(const BatchMat* mats, int count, const Params* P, double alpha, 
     const float d0 = cf.d0[m.model];
     const double s0 = cf.shift0[m.model];
     const double scale = P[b].scale, shift = P[b].shift;
-    const int64_t total = m.np * m.np;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / m.np, j = e - i * m.np;
-        double x = 0.0;
-        if (i < m.n && j < m.n) {
-            x = scale * m.H[i * m.ldh + j] + (i == j ? shift : 0.0);
-            x = alpha * x + (i == j ? (1.0 - alpha) * mu0 : 0.0);
+    const uint32_t qrow = (uint32_t)(m.np / 4), quads = (uint32_t)(m.np * m.np / 4);
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += gridDim.x * blockDim.x) {
+        const uint32_t i = q / qrow, j0 = 4 * (q - i * qrow);
+        const int64_t e0 = (int64_t)i * m.np + j0;
+        double x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = j0 + k;
+            x[k] = 0.0;
+            if (i < m.n && j < m.n) {
+                double v = scale * m.H[i * m.ldh + j] + (i == j ? shift : 0.0);
+                x[k] = alpha * v + (i == j ? (1.0 - alpha) * mu0 : 0.0);
+            }
         }
-        const float xf = (float)x;
-        m.X[e] = xf;
-        m.A[e] = d0 * xf;
-        const float xs = i == j ? (float)(x + s0) : xf;
-        const bool pad = i >= m.n || j >= m.n;   // the other buffer's padding too (no epilogue writes it)
-        uint16_t h, l;
-        if (three) {
-            uint16_t md;
-            split3(xs, h, md, l);
-            m.mid[0][e] = md;
-            if (pad) m.mid[1][e] = md;
-        } else {
-            split16<BF>(xs, h, l);
+        floatx4 xf, af;
+        uint16_t h[4], l[4], md[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            xf[k] = (float)x[k];
+            af[k] = d0 * xf[k];
+            const float xs = i == j0 + k ? (float)(x[k] + s0) : xf[k];
+            if (three) split3(xs, h[k], md[k], l[k]);
+            else split16<BF>(xs, h[k], l[k]);
         }
-        m.hi[0][e] = h;
-        m.lo[0][e] = l;
-        if (pad) {
-            m.hi[1][e] = h;
-            m.lo[1][e] = l;
+        *reinterpret_cast<floatx4*>(m.X + e0) = xf;
+        *reinterpret_cast<floatx4*>(m.A + e0) = af;
+        auto pack = [](const uint16_t* v) {
+            return u32x2{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16)};
+        };
+        *reinterpret_cast<u32x2*>(m.hi[0] + e0) = pack(h);
+        *reinterpret_cast<u32x2*>(m.lo[0] + e0) = pack(l);
+        if (three) *reinterpret_cast<u32x2*>(m.mid[0] + e0) = pack(md);
+        // the other buffer's padding too (no epilogue writes it)
+        if (i >= m.n || j0 + 3 >= m.n) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (i < m.n && j0 + k < m.n) continue;
+                m.hi[1][e0 + k] = h[k];
+                m.lo[1][e0 + k] = l[k];
+                if (three) m.mid[1][e0 + k] = md[k];
+            }
         }
     }
 }
@@ -395,7 +410,7 @@ hipError_t launch_batch_bounds(const BatchMat* mats, int count, Params* P, hipSt
 
 hipError_t launch_batch_rescale(const BatchMat* mats, int count, int64_t max_np, const Params* P,
                                 double alpha, BatchCoef cf, int bf16, hipStream_t s) {
-    int chunks = (int)((max_np * max_np + 4095) / 4096);
+    int chunks = (int)((max_np * max_np / 4 + 1023) / 1024);
     if (chunks < 1) chunks = 1;
     if (chunks > 64) chunks = 64;
     dim3 grid(chunks, count);

@@ -173,46 +173,84 @@ __device__ inline void split16(float x, uint16_t& h, uint16_t& l) {
 }
 
 template <bool BF>
+__device__ inline void rescale_quad(const RescaleArgs& a, double scale, double shift, int64_t i,
+                                    int64_t j0) {
+    const int64_t e0 = i * a.np + j0;
+    double x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = j0 + k;
+        x[k] = 0.0;
+        if (i < a.n && j < a.n) {
+            double v = scale * a.H[i * a.ldh + j] + (i == j ? shift : 0.0);
+            v = a.alpha * v + (i == j ? (1.0 - a.alpha) * a.mu0 : 0.0);
+            if (a.X0out) a.X0out[i * a.ldx + j] = (float)v;
+            x[k] = v;
+        }
+    }
+    if (a.mode == 2) {
+        *reinterpret_cast<double2*>(a.X64 + e0) = double2{x[0], x[1]};
+        *reinterpret_cast<double2*>(a.X64 + e0 + 2) = double2{x[2], x[3]};
+        *reinterpret_cast<double2*>(a.A64 + e0) = double2{a.d0 * x[0], a.d0 * x[1]};
+        *reinterpret_cast<double2*>(a.A64 + e0 + 2) = double2{a.d0 * x[2], a.d0 * x[3]};
+        return;
+    }
+    const float d0f = (float)a.d0;
+    split::floatx4 xf, af;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        xf[k] = (float)x[k];
+        af[k] = d0f * xf[k];
+    }
+    *reinterpret_cast<split::floatx4*>(a.X32 + e0) = xf;
+    *reinterpret_cast<split::floatx4*>(a.A32 + e0) = af;
+    if (a.mode != 0) return;
+    uint16_t h[4], l[4], md[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float xs = i == j0 + k ? (float)(x[k] + a.op_shift) : xf[k];
+        if (a.three) split::split3(xs, h[k], md[k], l[k]);
+        else split16<BF>(xs, h[k], l[k]);
+    }
+    auto pack = [](const uint16_t* v) {
+        return split::u32x2{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16)};
+    };
+    *reinterpret_cast<split::u32x2*>(a.hi + e0) = pack(h);
+    *reinterpret_cast<split::u32x2*>(a.lo + e0) = pack(l);
+    if (a.three) *reinterpret_cast<split::u32x2*>(a.mid + e0) = pack(md);
+    // the other buffer's padding (rows or columns >= n), which no layer epilogue writes
+    if (i >= a.n || j0 + 3 >= a.n) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i < a.n && j0 + k < a.n) continue;
+            if (a.hi1) {
+                a.hi1[e0 + k] = h[k];
+                a.lo1[e0 + k] = l[k];
+            }
+            if (a.three && a.mid1) a.mid1[e0 + k] = md[k];
+        }
+    }
+}
+
+// The rescaled start matrix X0 (FP32 or FP64 master), the accumulator A = d0 X0 and, for the
+// 16-bit modes, the split operands, over the padded np x np matrix (zero padding). Four
+// consecutive columns per thread (16-byte stores; np is a multiple of 4), quads in a grid-stride
+// loop.
+template <bool BF>
 __global__ void __launch_bounds__(256) k_rescale(RescaleArgs a) {
     const Params* P = a.P;
     const double scale = P->scale, shift = P->shift;
-    const int64_t total = a.np * a.np;
-    const float d0f = (float)a.d0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / a.np, j = e - i * a.np;
-        double x = 0.0;
-        if (i < a.n && j < a.n) {
-            x = scale * a.H[i * a.ldh + j] + (i == j ? shift : 0.0);
-            x = a.alpha * x + (i == j ? (1.0 - a.alpha) * a.mu0 : 0.0);
-            if (a.X0out) a.X0out[i * a.ldx + j] = (float)x;
+    const int64_t qrow = a.np / 4, quads = a.np * qrow;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    if (quads <= 0xffffffffLL) {
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += step) {
+            const uint32_t i = (uint32_t)q / (uint32_t)qrow, jq = (uint32_t)q - i * (uint32_t)qrow;
+            rescale_quad<BF>(a, scale, shift, i, 4 * (int64_t)jq);
         }
-        if (a.mode == 2) {
-            a.X64[e] = x;
-            a.A64[e] = a.d0 * x;
-        } else {
-            const float xf = (float)x;
-            a.X32[e] = xf;
-            a.A32[e] = d0f * xf;
-            if (a.mode == 0) {
-                const float xs = i == j ? (float)(x + a.op_shift) : xf;
-                const bool pad = i >= a.n || j >= a.n;
-                uint16_t h, l;
-                if (a.three) {
-                    uint16_t m;
-                    split::split3(xs, h, m, l);
-                    a.mid[e] = m;
-                    if (pad && a.mid1) a.mid1[e] = m;
-                } else {
-                    split16<BF>(xs, h, l);
-                }
-                a.hi[e] = h;
-                a.lo[e] = l;
-                if (a.hi1 && pad) {
-                    a.hi1[e] = h;
-                    a.lo1[e] = l;
-                }
-            }
+    } else {
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += step) {
+            const int64_t i = q / qrow;
+            rescale_quad<BF>(a, scale, shift, i, 4 * (q - i * qrow));
         }
     }
 }
@@ -281,7 +319,8 @@ hipError_t launch_bounds_params(const double* H, int64_t n, int64_t ldh, double 
 }
 
 hipError_t launch_rescale(const RescaleArgs& a, hipStream_t s) {
-    int64_t total = a.np * a.np;
+    if (a.np % 4 != 0) return hipErrorInvalidValue;
+    int64_t total = a.np * a.np / 4;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (a.bf16)
