@@ -536,6 +536,49 @@ SIGNATURES.update({
 BATCH_LAUNCH = {"layers": 0, "queue": 1}   # FE_BATCH_LAUNCH_*
 
 
+def _batch_outputs(mats, want_D, d_dtype, with_S):
+    """The fe_batch_item array for `mats` (dicts with H, mu, kT) and the output tensors it points
+    to: D list, tr [count, 2] (Tr D, sum D_ij^2), S [count], status [count]; plus the sum of the
+    padded sizes squared (arena elements)."""
+    import torch
+    count = len(mats)
+    dev = mats[0]["H"].device
+    d_dtype = d_dtype or torch.float32
+    D_list = []
+    tr = torch.zeros((count, 2), dtype=torch.float64, device=dev)
+    S = torch.zeros(count, dtype=torch.float64, device=dev)
+    status = torch.zeros(count, dtype=torch.int32, device=dev)
+    arr = (fe_batch_item * count)()
+    elems = 0
+    for b, m in enumerate(mats):
+        n, ldh = _check_H(m["H"])
+        D = torch.empty((n, n), dtype=d_dtype, device=dev) if want_D else None
+        D_list.append(D)
+        arr[b] = fe_batch_item(m["H"].data_ptr(), n, ldh, float(m["mu"]), float(m["kT"]),
+                               D.data_ptr() if want_D else None, n if want_D else 0,
+                               int(d_dtype == torch.float64),
+                               tr.data_ptr() + 16 * b, tr.data_ptr() + 16 * b + 8,
+                               S.data_ptr() + 8 * b if with_S else None)
+        np_ = -(-n // 128) * 128
+        elems += np_ * np_
+    return arr, D_list, tr, S, status, elems
+
+
+def batched_expand(mats, model, prec="fp16x2", model_s=None, alpha=1.0, ws=None, d_dtype=None):
+    """fe_batched_expand: one-shot batch (plan, launch, wait, destroy) on the current stream.
+    Returns (D list, tr [count, 2], S [count] (with model_s), status [count])."""
+    arr, D, tr, S, status, elems = _batch_outputs(mats, True, d_dtype, model_s is not None)
+    if prec == "bf16x3":   # 20 instead of 16 bytes of the arena per padded element
+        elems = -(-elems * 20 // 16)
+    ws = ws or Workspace(128, max_batch=len(mats), batch_elems=elems)
+    m = _model_of(model)
+    ms = _model_of(model_s) if model_s is not None else None
+    _check(lib().fe_batched_expand(arr, len(mats), C.byref(m.struct),
+                                   C.byref(ms.struct) if ms else None, float(alpha), PREC[prec],
+                                   C.c_void_p(status.data_ptr()), ws.handle, _stream_ptr()))
+    return D, tr, S, status
+
+
 class BatchPlan:
     """A captured batch (fe_batch_plan_create): `launch()` replays it on the current stream.
     By default every layer of every matrix runs in one queue launch (`set_launch`).
@@ -551,29 +594,10 @@ class BatchPlan:
 
     def __init__(self, mats, model, prec="fp16x2", model_s=None, alpha=1.0, ws=None,
                  want_D=True, d_dtype=None, with_entropy=False):
-        import torch
         self.count = len(mats)
-        dev = mats[0]["H"].device
-        d_dtype = d_dtype or torch.float32
         self.H = [m["H"] for m in mats]
-        self.D = []
-        self.tr = torch.zeros((self.count, 2), dtype=torch.float64, device=dev)
-        self.S = torch.zeros(self.count, dtype=torch.float64, device=dev)
-        self.status = torch.zeros(self.count, dtype=torch.int32, device=dev)
-        arr = (fe_batch_item * self.count)()
-        elems = 0
-        for b, m in enumerate(mats):
-            n, ldh = _check_H(m["H"])
-            D = torch.empty((n, n), dtype=d_dtype, device=dev) if want_D else None
-            self.D.append(D)
-            arr[b] = fe_batch_item(m["H"].data_ptr(), n, ldh, float(m["mu"]), float(m["kT"]),
-                                   D.data_ptr() if want_D else None, n if want_D else 0,
-                                   int(d_dtype == torch.float64),
-                                   self.tr.data_ptr() + 16 * b, self.tr.data_ptr() + 16 * b + 8,
-                                   self.S.data_ptr() + 8 * b
-                                   if (model_s is not None or with_entropy) else None)
-            np_ = -(-n // 128) * 128
-            elems += np_ * np_
+        arr, self.D, self.tr, self.S, self.status, elems = _batch_outputs(
+            mats, want_D, d_dtype, model_s is not None or with_entropy)
         self._items = arr
         if prec == "bf16x3":   # 20 instead of 16 bytes of the arena per padded element
             elems = -(-elems * 20 // 16)

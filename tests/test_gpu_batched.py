@@ -262,3 +262,23 @@ def test_bf16x3_plan_tiles(api, paper_model):
     plan.launch()
     torch.cuda.synchronize()
     assert plan.status.cpu().numpy().tolist() == [0] * 3
+
+
+def test_batched_expand_one_shot(api, paper_model):
+    """fe_batched_expand (plan, launch, wait, destroy in one call): the same D, traces, S and
+    status as a captured plan of the same batch, and the oracle's D within the bar."""
+    m = paper_model
+    mats = uneven_batch(6, 1300)
+    print("case one-shot batch6 fp16x2 with entropy", flush=True)
+    D, tr, S, status = api.batched_expand(mats, m, prec="fp16x2", model_s=m, alpha=0.842704)
+    assert status.cpu().numpy().tolist() == [0] * 6
+    plan = api.BatchPlan(mats, m, prec="fp16x2", model_s=m, alpha=0.842704)
+    plan.launch()
+    torch.cuda.synchronize()
+    for b, it in enumerate(mats):
+        assert torch.equal(D[b], plan.D[b]), f"item {b}"
+        Drec, _ = R.mlsp2_density(it["Hn"], it["mu"], it["kT"], m.theta, m.beta0, m.mu0)
+        n = Drec.shape[0]
+        assert np.linalg.norm(D[b].double().cpu().numpy() - Drec) / n <= 1e-5
+    assert torch.equal(tr, plan.tr) and torch.equal(S, plan.S)
+    plan.close()
