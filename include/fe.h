@@ -22,8 +22,11 @@
  *     them. "host" pointers are ordinary host memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call is
  *     asynchronous on that stream unless its comment says it synchronizes.
- *   - No call allocates device memory except fe_workspace_create. A workspace must not be
- *     used by two calls that overlap in time (e.g. on two streams).
+ *   - The expansions allocate no device memory: it is allocated by fe_workspace_create, by
+ *     batch plans (their tables and captured graph, when created or rebuilt), and by the
+ *     trainers and fe_autotune (scratch for the call, freed before they return);
+ *     fe_expand_density_noalloc uses no workspace at all. A workspace must not be used by two
+ *     calls that overlap in time (e.g. on two streams).
  *   - Return value: FE_OK (0), a positive warning (the result is still produced), or a
  *     negative error (nothing was enqueued, unless stated). fe_last_error() gives a message.
  *   - Conditions found on the device (non-finite H, mu outside the spectral bounds) cannot be
