@@ -251,8 +251,9 @@ int fe_batch_plan_launch(fe_batch_plan* plan, void* stream);
  * replaces the captured graph; on failure the plan is left empty and its launches fail. */
 int fe_batch_plan_retile(fe_batch_plan* plan, int32_t tile);
 
-/* How a plan runs the layers of a pass. FE_BATCH_LAUNCH_QUEUE (the default): every layer of every
- * matrix in one launch: each matrix's (tile, layer) work items sit in the queue of one XCD in
+/* How a plan runs the layers of a pass. FE_BATCH_LAUNCH_QUEUE (the default for batches whose
+ * first layer holds at least two 128 x 128 tiles per compute unit; smaller batches, bound by their
+ * chain of layers, default to FE_BATCH_LAUNCH_LAYERS): every layer of every matrix in one launch: each matrix's (tile, layer) work items sit in the queue of one XCD in
  * layer-major order; a workgroup takes the next item of its XCD's queue and starts it once the
  * matrix has completed its previous layer (bounded waits; the XCD is read from the hardware, so
  * the L2 that holds the matrix is the one its readers use). It needs the device to deal

@@ -37,12 +37,13 @@ inline int64_t batch_queue_counters(int nq, int count) { return nq + 2 * (int64_
 // Zeroes Q's counters (a kernel, so that the plan's captured graph holds no memset node).
 hipError_t launch_batch_queue_reset(const BatchQueue& Q, int count, hipStream_t s);
 // One pass over every layer of every matrix (q.layer, q.parity and q.map unused) on `grid`
-// workgroups: the number of queues times the longest queue (the hardware deals workgroup g to
-// XCD g % nq).
+// workgroups: the number of queues times the longest queue (the hardware deals consecutive
+// workgroups to consecutive XCDs, so each XCD gets the same number).
 hipError_t launch_batch_queue(const BatchLayerArgs& q, const BatchQueue& Q, int64_t grid, int bf16,
                               int tile, hipStream_t s);
-// Whether the queue launch's assumptions hold on the current device with nq XCDs: workgroup g
-// runs on XCD g % nq and reads that XCD's id from the hardware (a probe launch; synchronizes).
+// Whether the queue launch's assumptions hold on the current device with nq XCDs: consecutive
+// workgroups run on consecutive XCDs (round-robin, from whichever XCD the dispatch starts at), and
+// each reads its XCD's id from the hardware (a probe launch; synchronizes).
 hipError_t batch_queue_probe(int nq, bool* ok);
 // After the pass: a matrix whose items did not all complete, or one of whose waits gave up,
 // gets status FE_ERR_HIP (its traces then become NaN in the reduction).

@@ -136,7 +136,8 @@ __device__ inline void tile_coords(int t, int T, int& I, int& J) {
 }
 
 // Tile of data-parallel workgroup b among ntiles: the hardware deals workgroups to the 8 XCDs
-// round-robin, so workgroup b runs on XCD b % 8; each XCD is given a contiguous run of tiles.
+// round-robin, so the workgroups b with one value of b % 8 share an XCD (which one depends on where
+// the dispatch starts); each XCD is given a contiguous run of tiles.
 __device__ inline int xcd_tile(int b, int ntiles) {
     const int per = ntiles / 8;
     return b < 8 * per ? (b % 8) * per + b / 8 : b;

@@ -4,7 +4,8 @@
 //
 // The upper tiles [dp_tiles, ntiles) of one layer, times their nk K-blocks each, form a list of
 // (tile, K-block) iterations. The grid is split into `groups` groups (8: one per XCD, since the
-// hardware hands workgroup w to XCD w % 8); group g owns a contiguous run of those tiles and
+// hardware hands consecutive workgroups to consecutive XCDs, so the workgroups w with one value of
+// w % 8 share an XCD); group g owns a contiguous run of those tiles and
 // deals its iterations to its GX = grid / groups workgroups in contiguous, near-equal ranges.
 // A workgroup whose range stops inside a tile publishes that partial tile; the workgroup that
 // reaches the tile's last K-block adds the earlier contributors' partials in a fixed order.
