@@ -167,3 +167,28 @@ def test_autotune_chooses_tile_and_launch_form(api, paper_model):
         for b in range(plan.count):
             assert float((plan.D[b] - ref[0][b]).abs().max()) < 1e-4
     plan.close()
+
+
+def test_queue_launch_beside_other_work(api, paper_model):
+    """The queue launch while another stream keeps the GPU busy (FP32 products): its workgroups
+    then share the CUs with the other kernels and the dispatcher's round-robin starts wherever
+    that work left it; the results stay bitwise equal to the per-layer launches."""
+    mats = uneven_batch(48, 4700)
+    plan = api.BatchPlan(mats, paper_model, prec="fp16x2")
+    plan.set_launch("layers")
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = snapshot(plan)
+    plan.set_launch("queue")
+    side = torch.cuda.Stream()
+    a = torch.randn(2048, 2048, device="cuda")
+    b = torch.randn(2048, 2048, device="cuda")
+    print("case queue-launch batch48 beside FP32 products on another stream", flush=True)
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            for _ in range(20):
+                a = (a @ b) * 1e-3
+        plan.launch()
+        torch.cuda.synchronize()
+        assert_same(plan, ref, f"queue launch beside other work, replay {rep}")
+    plan.close()
