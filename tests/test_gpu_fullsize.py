@@ -76,6 +76,7 @@ def test_batch1024_sampled_against_oracle(api):
     mats = [dict(H=torch.from_numpy(it["H"]).cuda(), mu=it["mu"], kT=it["kT"]) for it in items]
     print("case batch1024 fp16x2", flush=True)
     plan = api.BatchPlan(mats, m, prec="fp16x2")
+    assert plan.launch_form == "queue"   # a batch that fills the GPU defaults to the queue launch
     plan.launch()
     torch.cuda.synchronize()
     assert int(np.count_nonzero(plan.status.cpu().numpy())) == 0
