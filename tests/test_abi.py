@@ -85,3 +85,39 @@ def test_tuner_and_plan_argument_errors_without_device(lib):
     assert lib.fe_batch_plan_autotune(None, None, ctypes.byref(i32), ms) == api.FE_ERR_ARG
     assert lib.fe_batch_plan_launch(None, None) == api.FE_ERR_ARG
     assert lib.fe_batch_plan_destroy(None) == api.FE_OK
+    # launch form and plan queries on a NULL plan
+    assert lib.fe_batch_plan_set_launch(None, api.BATCH_LAUNCH["queue"]) == api.FE_ERR_ARG
+    assert lib.fe_batch_plan_get(None, ctypes.byref(i32), None) == api.FE_ERR_ARG
+    # plan creation: output pointer, precision, workspace, then an empty batch
+    plan = ctypes.c_void_p()
+    rc = lib.fe_batch_plan_create(None, 0, None, None, 0.0, api.PREC["fp16x2"], None, None, None)
+    assert rc == api.FE_ERR_ARG and b"out" in lib.fe_last_error()
+    rc = lib.fe_batch_plan_create(None, 1, None, None, 0.0, api.PREC["fp32"], None, None,
+                                  ctypes.byref(plan))
+    assert rc == api.FE_ERR_ARG and b"FP16x2" in lib.fe_last_error() and plan.value is None
+    rc = lib.fe_batch_plan_create(None, 1, None, None, 0.0, api.PREC["fp16x2"], None, None,
+                                  ctypes.byref(plan))
+    assert rc == api.FE_ERR_ARG and b"workspace" in lib.fe_last_error()
+    rc = lib.fe_batched_expand(None, 0, None, None, 0.0, api.PREC["fp16x2"], None, None, None)
+    assert rc == api.FE_ERR_ARG
+    # queue layout: tile size, queue count, sizes that are not whole tiles
+    np_ = (ctypes.c_int64 * 2)(128, 192)
+    L = (ctypes.c_int32 * 2)(3, 2)
+    qoff = (ctypes.c_int32 * 17)()
+    nitems = ctypes.c_int64()
+    assert lib.fe_batch_queue_layout(2, np_, L, 96, 8, None, 0, qoff,
+                                     ctypes.byref(nitems)) == api.FE_ERR_ARG
+    assert lib.fe_batch_queue_layout(2, np_, L, 64, 17, None, 0, qoff,
+                                     ctypes.byref(nitems)) == api.FE_ERR_ARG
+    assert lib.fe_batch_queue_layout(2, np_, L, 128, 8, None, 0, qoff,
+                                     ctypes.byref(nitems)) == api.FE_ERR_ARG
+    assert b"multiple of the tile" in lib.fe_last_error()
+    assert lib.fe_batch_queue_layout(0, np_, L, 64, 8, None, 0, qoff,
+                                     ctypes.byref(nitems)) == api.FE_ERR_ARG
+    # counting only (items NULL), then a buffer one item too small
+    assert lib.fe_batch_queue_layout(2, np_, L, 64, 8, None, 0, qoff,
+                                     ctypes.byref(nitems)) == api.FE_OK
+    assert nitems.value > 0 and qoff[8] == nitems.value
+    small = (ctypes.c_int32 * (4 * nitems.value))()
+    assert lib.fe_batch_queue_layout(2, np_, L, 64, 8, small, nitems.value - 1, qoff,
+                                     ctypes.byref(nitems)) == api.FE_ERR_ARG
