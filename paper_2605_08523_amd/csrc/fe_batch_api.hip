@@ -515,7 +515,8 @@ int build_plan(fe_batch_plan* plan, int tile) {
             v.q.done = counters + nq;
             v.q.err = counters + nq + count;
             const bool giveup = g_queue_giveup.load() != 0;
-            v.q.spin_limit = giveup ? 64 : (1 << 20);   // 1 << 20: ~1 s of polls
+            // 1 << 20 polls, each after up to 16 x 512 clocks of sleep: ~5 s
+            v.q.spin_limit = giveup ? 64 : (1 << 20);
             v.q.need_offset = giveup ? (1 << 30) : 0;
             v.grid = longest * nq;
         };
