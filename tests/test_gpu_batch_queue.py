@@ -48,7 +48,7 @@ def assert_same(plan, ref, what):
 
 
 CASES = [("fp16x2", 128, "single"), ("fp16x2", 64, "single"), ("bf16x3", 128, "single"),
-         ("fp16x2", 128, "bank")]
+         ("bf16x2", 128, "single"), ("fp16x2", 128, "bank"), ("fp16x2", 64, "bank")]
 
 
 @pytest.mark.parametrize("prec,tile,kind", CASES)
